@@ -1,0 +1,129 @@
+/*
+ * mms.h — C ABI of libmms, a multiway mergesort of 32-bit keys and stable
+ * key-value pairs on an AMD Instinct MI355X (gfx950).
+ *
+ * Method: Casanova, Iacono, Karsin, Sitchinava, Weichert, "An Efficient
+ * Multiway Mergesort for GPU Architectures" (arXiv 1702.07961).  A sort is a
+ * base-case pass that sorts tiles of T keys on chip (§4.3), followed by
+ * ceil(log_K(ceil(n/T))) merge rounds (§6.2); each round splits every group
+ * of K sorted runs into independent output tiles at exact split indices
+ * (§4.1, parallel partitioning) and merges each tile's K pieces through LDS
+ * (§4.2, I/O-efficient merging; §7 names this partition-then-merge variant).
+ *
+ * Conventions shared by every call:
+ *   - Return value: an MMS_* status.  A negative status leaves a message in
+ *     the calling thread's mms_last_error().  No C++ exception crosses the ABI.
+ *   - Device pointers ("d_") are HIP device allocations owned by the caller;
+ *     the library never frees caller memory.  Host pointers ("h_") are read
+ *     during the call only.
+ *   - Asynchrony: work is enqueued on the caller's stream (a hipStream_t
+ *     passed as void*, NULL = the null stream).  The call returns after
+ *     enqueueing; buffers must stay valid until that work completes.  Errors
+ *     detected while enqueueing are returned; a fault inside a kernel
+ *     surfaces as MMS_EHIP at the next synchronising call.
+ *   - Sizes: n counts elements.  n == 0 is a no-op returning MMS_OK.
+ *     n >= 2^32 returns MMS_EINVAL (positions are 32-bit on the device).
+ */
+#ifndef MMS_H
+#define MMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MMS_OK 0
+#define MMS_PENDING 1
+#define MMS_EINVAL (-1)
+#define MMS_ENOMEM (-2)
+#define MMS_EHIP (-3)
+#define MMS_ENOENT (-4)
+#define MMS_ESHUTDOWN (-5)
+
+/* flags */
+#define MMS_PAIRS 0x1u    /* workspace sizing: key-value pairs                */
+#define MMS_KEY_I32 0x2u  /* keys are int32 (signed order) instead of uint32  */
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* mms_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int mms_version(void);
+
+/*
+ * Sort plan (host only, no device work): the tile and fan-out parameters the
+ * sort of n elements will use and the number of global-memory passes, which
+ * is 1 (base case) + rounds, rounds = ceil(log_K(ceil(n / tile))) (§6.2).
+ */
+typedef struct {
+    uint64_t n;
+    uint32_t flags;
+    uint32_t tile;          /* base-case tile size T in elements            */
+    uint32_t lanes_per_tile;/* threads of one base-case workgroup            */
+    uint32_t fanout;        /* merge fan-out K                              */
+    uint32_t merge_tile;    /* output tile of one merge workgroup           */
+    uint32_t rounds;        /* merge rounds                                  */
+    uint32_t passes;        /* 1 + rounds                                   */
+    uint64_t workspace_bytes;
+} mms_plan_t;
+
+int mms_plan(uint64_t n, uint32_t flags, mms_plan_t* out);
+
+/* Bytes of device workspace the sort of n elements needs (flags: MMS_PAIRS). */
+size_t mms_workspace_bytes(uint64_t n, uint32_t flags);
+
+/*
+ * Sort n keys ascending (§4: the problem statement; the result is the sorted
+ * multiset).  d_in and d_out hold n uint32 (int32 with MMS_KEY_I32); they
+ * may be the same buffer, but must not partially overlap.  d_ws is a device
+ * buffer of at least mms_workspace_bytes(n, flags) bytes, 256-byte aligned,
+ * not overlapping d_in or d_out.  Errors: MMS_EINVAL (bad pointer, size,
+ * flags, overlap or workspace), MMS_EHIP (launch failure).
+ */
+int mms_sort_u32(const uint32_t* d_in, uint32_t* d_out, uint64_t n,
+                 void* d_ws, size_t ws_bytes, uint32_t flags, void* stream);
+
+/*
+ * Stable sort of n (key, value) pairs by key: equal keys keep their input
+ * order, so the output is unique (the order of (key, input index) pairs).
+ * Same rules as mms_sort_u32; workspace from
+ * mms_workspace_bytes(n, flags | MMS_PAIRS).  d_kin may equal d_kout and
+ * d_vin may equal d_vout.
+ */
+int mms_sort_pairs_u32(const uint32_t* d_kin, const uint32_t* d_vin,
+                       uint32_t* d_kout, uint32_t* d_vout, uint64_t n,
+                       void* d_ws, size_t ws_bytes, uint32_t flags, void* stream);
+
+/*
+ * §4.1 parallel partitioning on its own: split indices of groups of K sorted
+ * runs at given ranks.  The n elements of d_keys form groups of K runs laid
+ * out back to back: run k of group g starts at g*K*run_len + k*run_len and
+ * has min(run_len, remaining) elements (so only the last group may be short
+ * or hold fewer than K runs).  For each query q < nqueries, with group
+ * d_group[q] and rank d_rank[q] (0 <= rank <= size of that group),
+ * d_split[q*K + k] receives the number of elements of run k among the first
+ * `rank` elements of the group's merged order, where equal keys are ordered
+ * by (run index, position); entries for runs the group lacks are 0.  Runs
+ * must be sorted in the key order that flags select.  d_group, d_rank
+ * (uint64) and d_split (uint32, nqueries*K) are device buffers.
+ * Errors: MMS_EINVAL for K outside [1, 16], run_len == 0 or n >= 2^32.
+ * A query whose group or rank is out of range yields an all-0xFFFFFFFF row.
+ */
+int mms_partition_u32(const uint32_t* d_keys, uint64_t n, uint64_t run_len, uint32_t K,
+                      const uint64_t* d_group, const uint64_t* d_rank, uint64_t nqueries,
+                      uint32_t* d_split, uint32_t flags, void* stream);
+
+/*
+ * Streaming copy of n uint32 (d_in -> d_out), the bandwidth probe the
+ * sort's passes are compared with.  Buffers must not overlap.
+ */
+int mms_copy_u32(const uint32_t* d_in, uint32_t* d_out, uint64_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MMS_H */

@@ -1,0 +1,127 @@
+"""MI355X multiway mergesort (arXiv 1702.07961) — Python front end.
+
+Thin wrappers over the C ABI in ``include/mms.h``: PyTorch supplies device
+memory and the stream, ``libmms.so`` does every step of the sort in HIP
+kernels.  Importing this package does not load the library; the first call
+does, and fails loudly if it has not been built.
+"""
+from __future__ import annotations
+
+from . import _lib
+from ._lib import MMS_KEY_I32, MMS_PAIRS, MmsError, MmsPlan  # noqa: F401
+
+__all__ = ["sort", "sort_pairs", "partition", "copy", "plan", "workspace_bytes", "MmsError"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _check_u32(t, name):
+    torch = _torch()
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype not in (torch.int32, torch.uint32):
+        raise ValueError(f"{name} must be int32/uint32, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def plan(n: int, pairs: bool = False, i32: bool = False) -> MmsPlan:
+    """Tile size, fan-out, rounds, passes and workspace for a sort of n elements."""
+    p = MmsPlan()
+    flags = (MMS_PAIRS if pairs else 0) | (MMS_KEY_I32 if i32 else 0)
+    _lib.check(_lib.lib().mms_plan(int(n), flags, p))
+    return p
+
+
+def workspace_bytes(n: int, pairs: bool = False) -> int:
+    return int(_lib.lib().mms_workspace_bytes(int(n), MMS_PAIRS if pairs else 0))
+
+
+def _workspace(n, pairs, device, workspace):
+    torch = _torch()
+    need = workspace_bytes(n, pairs)
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < need:
+            raise ValueError(f"workspace needs {need} bytes")
+        return workspace, need
+    if need == 0:
+        return None, 0
+    return torch.empty(need, dtype=torch.uint8, device=device), need
+
+
+def sort(keys, out=None, i32: bool | None = None, workspace=None, stream=None):
+    """Sort a 1-D int32/uint32 device tensor ascending; returns ``out``.
+
+    int32 tensors sort in signed order, uint32 in unsigned order, unless
+    ``i32`` says otherwise.  ``out`` may be ``keys`` itself (in place).
+    """
+    torch = _torch()
+    _check_u32(keys, "keys")
+    if i32 is None:
+        i32 = keys.dtype == torch.int32
+    n = keys.numel()
+    if out is None:
+        out = torch.empty_like(keys)
+    _check_u32(out, "out")
+    if out.numel() != n:
+        raise ValueError("out has the wrong size")
+    ws, need = _workspace(n, False, keys.device, workspace)
+    _lib.check(_lib.lib().mms_sort_u32(keys.data_ptr(), out.data_ptr(), n,
+                                       ws.data_ptr() if ws is not None else None, need,
+                                       MMS_KEY_I32 if i32 else 0, _stream_ptr(stream)))
+    return out
+
+
+def sort_pairs(keys, values, out_keys=None, out_values=None, i32: bool | None = None,
+               workspace=None, stream=None):
+    """Stable sort of (key, value) pairs by key; returns (out_keys, out_values)."""
+    torch = _torch()
+    _check_u32(keys, "keys")
+    _check_u32(values, "values")
+    if i32 is None:
+        i32 = keys.dtype == torch.int32
+    n = keys.numel()
+    if values.numel() != n:
+        raise ValueError("keys and values differ in size")
+    if out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if out_values is None:
+        out_values = torch.empty_like(values)
+    ws, need = _workspace(n, True, keys.device, workspace)
+    _lib.check(_lib.lib().mms_sort_pairs_u32(
+        keys.data_ptr(), values.data_ptr(), out_keys.data_ptr(), out_values.data_ptr(), n,
+        ws.data_ptr() if ws is not None else None, need, MMS_KEY_I32 if i32 else 0,
+        _stream_ptr(stream)))
+    return out_keys, out_values
+
+
+def partition(keys, run_len: int, K: int, groups, ranks, i32: bool = False, stream=None):
+    """§4.1 split indices; returns a (nqueries, K) uint32 device tensor."""
+    torch = _torch()
+    _check_u32(keys, "keys")
+    g = torch.as_tensor(groups, dtype=torch.int64, device=keys.device).contiguous()
+    r = torch.as_tensor(ranks, dtype=torch.int64, device=keys.device).contiguous()
+    nq = g.numel()
+    out = torch.empty((nq, K), dtype=torch.int32, device=keys.device)
+    _lib.check(_lib.lib().mms_partition_u32(keys.data_ptr(), keys.numel(), int(run_len), int(K),
+                                            g.data_ptr(), r.data_ptr(), nq, out.data_ptr(),
+                                            MMS_KEY_I32 if i32 else 0, _stream_ptr(stream)))
+    return out
+
+
+def copy(src, dst, stream=None):
+    _check_u32(src, "src")
+    _check_u32(dst, "dst")
+    _lib.check(_lib.lib().mms_copy_u32(src.data_ptr(), dst.data_ptr(), src.numel(),
+                                       _stream_ptr(stream)))
+    return dst

@@ -1,0 +1,94 @@
+"""ctypes binding of libmms (argument marshalling only).
+
+Every call maps one-to-one onto an ``extern "C"`` entry point of
+``include/mms.h``; all sorting work runs in the library's HIP kernels.  The
+library must be built (``paper_1702_07961_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmms.so")
+
+MMS_OK = 0
+MMS_PENDING = 1
+MMS_EINVAL = -1
+MMS_ENOMEM = -2
+MMS_EHIP = -3
+MMS_ENOENT = -4
+MMS_ESHUTDOWN = -5
+
+MMS_PAIRS = 0x1
+MMS_KEY_I32 = 0x2
+
+# every symbol include/mms.h declares
+EXPORTS = [
+    "mms_last_error", "mms_version", "mms_plan", "mms_workspace_bytes", "mms_sort_u32",
+    "mms_sort_pairs_u32", "mms_partition_u32", "mms_copy_u32",
+]
+
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+
+
+class MmsPlan(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint64),
+        ("flags", ctypes.c_uint32),
+        ("tile", ctypes.c_uint32),
+        ("lanes_per_tile", ctypes.c_uint32),
+        ("fanout", ctypes.c_uint32),
+        ("merge_tile", ctypes.c_uint32),
+        ("rounds", ctypes.c_uint32),
+        ("passes", ctypes.c_uint32),
+        ("workspace_bytes", ctypes.c_uint64),
+    ]
+
+
+class MmsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mms error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def _declare(lib):
+    lib.mms_last_error.restype = ctypes.c_char_p
+    lib.mms_last_error.argtypes = []
+    lib.mms_version.restype = ctypes.c_int
+    lib.mms_plan.argtypes = [_u64, _u32, ctypes.POINTER(MmsPlan)]
+    lib.mms_plan.restype = ctypes.c_int
+    lib.mms_workspace_bytes.argtypes = [_u64, _u32]
+    lib.mms_workspace_bytes.restype = ctypes.c_size_t
+    lib.mms_sort_u32.argtypes = [_vp, _vp, _u64, _vp, ctypes.c_size_t, _u32, _vp]
+    lib.mms_sort_u32.restype = ctypes.c_int
+    lib.mms_sort_pairs_u32.argtypes = [_vp, _vp, _vp, _vp, _u64, _vp, ctypes.c_size_t, _u32, _vp]
+    lib.mms_sort_pairs_u32.restype = ctypes.c_int
+    lib.mms_partition_u32.argtypes = [_vp, _u64, _u64, _u32, _vp, _vp, _u64, _vp, _u32, _vp]
+    lib.mms_partition_u32.restype = ctypes.c_int
+    lib.mms_copy_u32.argtypes = [_vp, _vp, _u64, _vp]
+    lib.mms_copy_u32.restype = ctypes.c_int
+    return lib
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmms.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1702_07961_amd.build` "
+                "(the HIP library is required; there is no CPU fallback)")
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def check(code: int) -> int:
+    if code < 0:
+        raise MmsError(code, lib().mms_last_error().decode())
+    return code

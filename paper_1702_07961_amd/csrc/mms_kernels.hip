@@ -1,0 +1,396 @@
+// gfx950 kernels of the multiway mergesort and their launchers.
+//
+//   tile_sort   base case (§4.3): sort tiles of T1 elements on chip
+//   corank      partition (§4.1): split indices of K sorted runs at a rank
+//   merge       K-way merge of one output tile through LDS (§4.2, §7)
+//   copy        streaming copy, the bandwidth probe
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mms_device.h"
+#include "mms_internal.h"
+
+namespace mms {
+
+// ===========================================================================
+// Base case: one workgroup of W1 waves sorts T1 = 64*E1*W1 elements.
+// Each wave loads a contiguous chunk of 64*E1 (coalesced, striped over the
+// lanes), sorts it in registers, and parks it in LDS; the W1 sorted chunks are
+// then merged level by level inside LDS, the last level straight to memory.
+// Missing elements of a ragged last tile are sentinels, which sort last and
+// are never stored.
+// ===========================================================================
+template <int E, int W, bool P>
+__global__ __launch_bounds__(W * 64) void k_tile_sort(const uint32_t* __restrict__ in_k,
+                                                      const uint32_t* __restrict__ in_v, uint32_t* out_k,
+                                                      uint32_t* out_v, uint64_t n, uint32_t flip_in,
+                                                      uint32_t flip_out) {
+    constexpr uint32_t CH = 64u * E;
+    constexpr uint32_t T = CH * W;
+    extern __shared__ uint32_t smem[];
+    uint32_t* Xk = smem;
+    uint32_t* Yk = smem + T;
+    uint32_t* Xv = P ? smem + 2 * T : nullptr;
+    uint32_t* Yv = P ? smem + 3 * T : nullptr;
+    uint32_t* seg0 = smem + (P ? 4 : 2) * T;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const uint64_t base = (uint64_t)blockIdx.x * T;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(T, n - base);
+
+    Elem<P> r[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t j = (uint32_t)wave * CH + (uint32_t)e * 64u + (uint32_t)lane;
+        if (j < cnt) {
+            if constexpr (P) r[e] = Elem<P>{in_k[base + j] ^ flip_in, j, in_v[base + j]};
+            else r[e] = Elem<P>{in_k[base + j] ^ flip_in};
+        } else {
+            r[e] = Elem<P>::sentinel();
+        }
+    }
+    wave_sort_blocked<E, P>(r, lane);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t idx = (uint32_t)wave * CH + (uint32_t)lane * E + (uint32_t)e;
+        Xk[idx] = r[e].k;
+        if constexpr (P) Xv[idx] = r[e].v;
+    }
+    if (threadIdx.x <= (unsigned)W) seg0[threadIdx.x] = threadIdx.x * CH;
+    __syncthreads();
+
+    for (uint32_t lvl = 0; (1u << lvl) < (uint32_t)W; ++lvl) {
+        const bool last = (2u << lvl) >= (uint32_t)W;
+        if (last) {
+            GlobalSinkLim<P> out{out_k + base, P ? out_v + base : nullptr, flip_out, cnt};
+            merge_level<kEM, P>(Xk, Xv, seg0, W, lvl, T, out, wave, W, lane);
+        } else {
+            LdsSink<P> out{Yk, Yv};
+            merge_level<kEM, P>(Xk, Xv, seg0, W, lvl, T, out, wave, W, lane);
+        }
+        __syncthreads();
+        uint32_t* t = Xk; Xk = Yk; Yk = t;
+        t = Xv; Xv = Yv; Yv = t;
+    }
+}
+
+// ===========================================================================
+// Partition (§4.1): split indices c_0..c_{K-1} of K sorted runs at rank r.
+//
+// Exact, with O(log L) dependent probe rounds.  At resolution h (a power of
+// two) call block j of run k its elements [j*h, (j+1)*h) and represent a full
+// block by its last element.  The number of run-k full blocks inside the
+// first r merged elements is floor(c_k / h), and the blocks inside form the
+// smallest such representatives overall (the first r elements are closed
+// downwards).  Their total t_h = sum_k floor(c_k/h) lies in
+// [ceil((r - K(h-1))/h), floor(r/h)], an interval narrower than K.
+// Going from resolution 2h to h, run k can only gain the two half-blocks of
+// blocks the previous level left undecided; every such candidate is probed
+// once, the candidates are ranked in the wave, and the bounds on t_h turn
+// into bounds [lo_k, hi_k] on floor(c_k/h) whose widths sum to less than K.
+// So at most 4K-2 candidates exist per level (one per lane for K <= 16), and
+// at h = 1 the bounds meet: c_k = lo_k = hi_k.  Ties are ordered by (key,
+// run, position), the stable order.
+// ===========================================================================
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, uint32_t l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (int)l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), (int)l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, int lane, uint32_t* total) {
+    uint32_t incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    *total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    return incl - x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, d, 64);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), d, 64);
+        x += ((uint64_t)hi << 32) | lo;
+    }
+    return x;
+}
+
+// Returns c_k in lane k (k < Kg); other lanes return 0.  All 64 lanes call.
+__device__ uint64_t corank_wave(const uint32_t* __restrict__ keys, uint64_t gb, uint64_t glen, uint64_t L,
+                                uint32_t Kg, uint64_t r, uint32_t flip, int lane) {
+    const bool own = (uint32_t)lane < Kg;
+    const uint64_t nk = own ? min(L, glen - (uint64_t)lane * L) : 0;
+    const uint64_t maxlen = Kg > 1 ? L : glen;
+    uint64_t s0 = 1;
+    while (s0 <= maxlen) s0 <<= 1;
+    uint64_t lo = 0, hi = 0;   // bounds on floor(c_k / h), lane k
+    for (uint64_t h = s0 >> 1; h >= 1; h >>= 1) {
+        const uint64_t nb = nk / h;                       // full blocks of run k at resolution h
+        const uint64_t jlo = 2 * lo;
+        const uint64_t jhi = min(2 * hi + 1, nb == 0 ? 0 : nb - 1);
+        const uint32_t cnt = (own && nb > jlo) ? (uint32_t)(jhi - jlo + 1) : 0u;
+        uint32_t total;
+        const uint32_t off = wave_excl_scan(cnt, lane, &total);
+
+        // candidate owned by this lane: run kk, block j
+        uint32_t kk = 0;
+        for (uint32_t k = 0; k < Kg; ++k)
+            if ((uint32_t)__builtin_amdgcn_readlane((int)off, (int)k) <= (uint32_t)lane) kk = k;
+        const bool valid = (uint32_t)lane < total;
+        const uint32_t my_off = (uint32_t)__shfl((int)off, (int)kk, 64);
+        const uint64_t my_jlo = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(jlo >> 0), (int)kk, 64)) |
+                                ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(jlo >> 32), (int)kk, 64) << 32);
+        const uint32_t local = (uint32_t)lane - my_off;
+        uint64_t comp = ~0ull;
+        if (valid) {
+            const uint64_t j = my_jlo + local;
+            const uint64_t pos = (j + 1) * h - 1;
+            const uint32_t key = keys[gb + (uint64_t)kk * L + pos] ^ flip;
+            comp = ((uint64_t)key << 32) | ((uint64_t)kk << 8) | (uint64_t)local;
+        }
+        uint32_t rank = 0;
+        for (uint32_t mu = 0; mu < total; ++mu) rank += readlane_u64(comp, mu) < comp ? 1u : 0u;
+
+        const uint64_t sum2lo = wave_sum_u64(own ? 2 * lo : 0);
+        const int64_t slack = (int64_t)Kg * (int64_t)(h - 1);
+        const int64_t num = (int64_t)r - slack;
+        const uint64_t tlo = num > 0 ? ((uint64_t)num + h - 1) / h : 0;
+        const uint64_t thi = r / h;
+        const uint64_t mlo = tlo > sum2lo ? min<uint64_t>(tlo - sum2lo, total) : 0;
+        const uint64_t mhi = thi > sum2lo ? min<uint64_t>(thi - sum2lo, total) : 0;
+        const uint64_t blo = __ballot(valid && rank < mlo);
+        const uint64_t bhi = __ballot(valid && rank < mhi);
+        const uint64_t mask = cnt ? (((cnt >= 64 ? ~0ull : ((1ull << cnt) - 1))) << off) : 0ull;
+        const uint64_t nlo = jlo + (uint64_t)__popcll(blo & mask);
+        const uint64_t nhi = jlo + (uint64_t)__popcll(bhi & mask);
+        lo = own ? nlo : 0;
+        hi = own ? nhi : 0;
+    }
+    return lo;
+}
+
+// One wave per tile of a merge round: the split at the tile's first output.
+__global__ __launch_bounds__(256) void k_corank_tiles(const uint32_t* __restrict__ src, uint64_t n, uint64_t L,
+                                                      uint32_t K, uint32_t Tout, uint64_t tpg, uint64_t tiles,
+                                                      uint32_t* __restrict__ table) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t t = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (t >= tiles) return;
+    const uint64_t g = t / tpg;
+    const uint64_t i = t - g * tpg;
+    const uint64_t gb = g * (uint64_t)K * L;
+    const uint64_t glen = min((uint64_t)K * L, n - gb);
+    const uint32_t Kg = (uint32_t)((glen + L - 1) / L);
+    uint64_t c = 0;
+    if (i > 0) c = corank_wave(src, gb, glen, L, Kg, i * (uint64_t)Tout, 0u, lane);
+    if ((uint32_t)lane < K) table[t * K + (uint64_t)lane] = (uint32_t)c;
+}
+
+__global__ __launch_bounds__(256) void k_corank_queries(const uint32_t* __restrict__ keys, uint64_t n,
+                                                        uint64_t L, uint32_t K, const uint64_t* __restrict__ qg,
+                                                        const uint64_t* __restrict__ qr, uint64_t nq,
+                                                        uint32_t* __restrict__ split, uint32_t flip) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t q = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (q >= nq) return;
+    const uint64_t g = qg[q];
+    const uint64_t r = qr[q];
+    const uint64_t groups = (n + (uint64_t)K * L - 1) / ((uint64_t)K * L);
+    bool ok = g < groups;
+    const uint64_t gb = g * (uint64_t)K * L;
+    const uint64_t glen = ok ? min((uint64_t)K * L, n - gb) : 0;
+    ok = ok && r <= glen;
+    if (!ok) {
+        if ((uint32_t)lane < K) split[q * K + (uint64_t)lane] = 0xFFFFFFFFu;
+        return;
+    }
+    const uint32_t Kg = (uint32_t)((glen + L - 1) / L);
+    const uint64_t c = corank_wave(keys, gb, glen, L, Kg, r, flip, lane);
+    if ((uint32_t)lane < K) split[q * K + (uint64_t)lane] = (uint32_t)c;
+}
+
+// ===========================================================================
+// Merge (§4.2, §7): one workgroup per output tile of a round.  The tile's
+// pieces of its group's K runs, bounded by the split indices of its first
+// and last output, are loaded into LDS back to back, merged pairwise level
+// by level inside LDS (log2 K levels), and the last level is written to
+// memory.  A group holding a single run is copied.
+// ===========================================================================
+template <int W, bool P>
+__global__ __launch_bounds__(W * 64) void k_merge(const uint32_t* __restrict__ src_k,
+                                                  const uint32_t* __restrict__ src_v, uint32_t* dst_k,
+                                                  uint32_t* dst_v, uint64_t n, uint64_t L, uint32_t K,
+                                                  uint32_t Tout, uint64_t tpg,
+                                                  const uint32_t* __restrict__ table, uint32_t flip_out) {
+    extern __shared__ uint32_t smem[];
+    uint32_t* Xk = smem;
+    uint32_t* Yk = smem + Tout;
+    uint32_t* Xv = P ? smem + 2 * Tout : nullptr;
+    uint32_t* Yv = P ? smem + 3 * Tout : nullptr;
+    uint32_t* seg0 = smem + (P ? 4 : 2) * Tout;   // [kMaxFanout + 1]
+    uint32_t* start = seg0 + kMaxFanout + 1;      // [kMaxFanout]
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const uint64_t t = blockIdx.x;
+    const uint64_t g = t / tpg;
+    const uint64_t i = t - g * tpg;
+    const uint64_t gb = g * (uint64_t)K * L;
+    const uint64_t glen = min((uint64_t)K * L, n - gb);
+    const uint32_t Kg = (uint32_t)((glen + L - 1) / L);
+    const uint64_t obeg = i * (uint64_t)Tout;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(Tout, glen - obeg);
+    const uint64_t obase = gb + obeg;
+
+    if (Kg == 1) {   // a lone run: its tile is already in order
+        for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
+            dst_k[obase + j] = src_k[obase + j] ^ flip_out;
+            if constexpr (P) dst_v[obase + j] = src_v[obase + j];
+        }
+        return;
+    }
+    if (threadIdx.x < Kg) {
+        const uint32_t k = threadIdx.x;
+        const uint64_t nk = min(L, glen - (uint64_t)k * L);
+        // the clamps only guard memory safety; exact splits never trigger them
+        const uint32_t s = i == 0 ? 0u : min(table[t * K + k], (uint32_t)nk);
+        const uint32_t e = (obeg + Tout >= glen) ? (uint32_t)nk : min(table[(t + 1) * K + k], (uint32_t)nk);
+        start[k] = s;
+        seg0[k + 1] = e > s ? e - s : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        seg0[0] = 0;
+        for (uint32_t k = 0; k < Kg; ++k) seg0[k + 1] = min(seg0[k + 1] + seg0[k], cnt);
+    }
+    __syncthreads();
+    for (uint32_t k = 0; k < Kg; ++k) {
+        const uint32_t dst0 = seg0[k], len = seg0[k + 1] - dst0;
+        const uint64_t src0 = gb + (uint64_t)k * L + start[k];
+        for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) {
+            Xk[dst0 + j] = src_k[src0 + j];
+            if constexpr (P) Xv[dst0 + j] = src_v[src0 + j];
+        }
+    }
+    __syncthreads();
+
+    for (uint32_t lvl = 0; (1u << lvl) < Kg; ++lvl) {
+        const bool last = (2u << lvl) >= Kg;
+        if (last) {
+            GlobalSinkLim<P> out{dst_k + obase, P ? dst_v + obase : nullptr, flip_out, cnt};
+            merge_level<kEM, P>(Xk, Xv, seg0, Kg, lvl, cnt, out, wave, W, lane);
+        } else {
+            LdsSink<P> out{Yk, Yv};
+            merge_level<kEM, P>(Xk, Xv, seg0, Kg, lvl, cnt, out, wave, W, lane);
+        }
+        __syncthreads();
+        uint32_t* tmp = Xk; Xk = Yk; Yk = tmp;
+        tmp = Xv; Xv = Yv; Yv = tmp;
+    }
+}
+
+// ===========================================================================
+// Streaming copy: 16 bytes per lane when both pointers allow it.
+// ===========================================================================
+__global__ __launch_bounds__(256) void k_copy_vec4(const uint4* __restrict__ in, uint4* __restrict__ out,
+                                                   uint64_t n4) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) out[i] = in[i];
+}
+__global__ __launch_bounds__(256) void k_copy_u32(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                  uint64_t beg, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = beg + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = in[i];
+}
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+RoundGeom round_geom(uint64_t n, uint64_t L, uint32_t K, uint32_t Tout) {
+    RoundGeom g{};
+    g.n = n;
+    g.L = L;
+    g.K = K;
+    g.Tout = Tout;
+    const uint64_t span = (uint64_t)K * L;
+    g.groups = (n + span - 1) / span;
+    g.tiles_per_group = (span + Tout - 1) / Tout;
+    const uint64_t last = n - (g.groups - 1) * span;
+    g.tiles = (g.groups - 1) * g.tiles_per_group + (last + Tout - 1) / Tout;
+    return g;
+}
+
+static hipError_t allow_lds(const void* f, size_t bytes) {
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_tile_sort(bool pairs, const uint32_t* in_k, const uint32_t* in_v, uint32_t* out_k,
+                            uint32_t* out_v, uint64_t n, uint32_t flip_in, uint32_t flip_out, hipStream_t s) {
+    const uint64_t blocks = (n + kT1 - 1) / kT1;
+    const size_t lds = ((pairs ? 4u : 2u) * kT1 + 32u) * sizeof(uint32_t);
+    if (pairs) {
+        hipError_t e = allow_lds((const void*)k_tile_sort<kE1, kW1, true>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_tile_sort<kE1, kW1, true>), dim3((unsigned)blocks), dim3(kW1 * 64), lds, s, in_k, in_v,
+                           out_k, out_v, n, flip_in, flip_out);
+    } else {
+        hipError_t e = allow_lds((const void*)k_tile_sort<kE1, kW1, false>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_tile_sort<kE1, kW1, false>), dim3((unsigned)blocks), dim3(kW1 * 64), lds, s, in_k,
+                           in_v, out_k, out_v, n, flip_in, flip_out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_corank_tiles(const uint32_t* src, const RoundGeom& g, uint32_t* table, hipStream_t s) {
+    const uint64_t blocks = (g.tiles + 3) / 4;
+    hipLaunchKernelGGL(k_corank_tiles, dim3((unsigned)blocks), dim3(256), 0, s, src, g.n, g.L, g.K, g.Tout,
+                       g.tiles_per_group, g.tiles, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_corank_queries(const uint32_t* keys, uint64_t n, uint64_t L, uint32_t K, const uint64_t* group,
+                                 const uint64_t* rank, uint64_t nq, uint32_t* split, uint32_t flip, hipStream_t s) {
+    const uint64_t blocks = (nq + 3) / 4;
+    hipLaunchKernelGGL(k_corank_queries, dim3((unsigned)blocks), dim3(256), 0, s, keys, n, L, K, group, rank, nq,
+                       split, flip);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(bool pairs, const uint32_t* src_k, const uint32_t* src_v, uint32_t* dst_k, uint32_t* dst_v,
+                        const RoundGeom& g, const uint32_t* table, uint32_t flip_out, hipStream_t s) {
+    const size_t lds = ((pairs ? 4u : 2u) * g.Tout + 2u * kMaxFanout + 8u) * sizeof(uint32_t);
+    if (pairs) {
+        hipError_t e = allow_lds((const void*)k_merge<kW3, true>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_merge<kW3, true>), dim3((unsigned)g.tiles), dim3(kW3 * 64), lds, s, src_k, src_v, dst_k,
+                           dst_v, g.n, g.L, g.K, g.Tout, g.tiles_per_group, table, flip_out);
+    } else {
+        hipError_t e = allow_lds((const void*)k_merge<kW3, false>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_merge<kW3, false>), dim3((unsigned)g.tiles), dim3(kW3 * 64), lds, s, src_k, src_v,
+                           dst_k, dst_v, g.n, g.L, g.K, g.Tout, g.tiles_per_group, table, flip_out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const uint32_t* in, uint32_t* out, uint64_t n, hipStream_t s) {
+    const unsigned blocks = 256u * 8u;
+    uint64_t done = 0;
+    if ((((uintptr_t)in | (uintptr_t)out) & 15u) == 0) {
+        const uint64_t n4 = n / 4;
+        if (n4) {
+            hipLaunchKernelGGL(k_copy_vec4, dim3(blocks), dim3(256), 0, s, (const uint4*)in, (uint4*)out, n4);
+        }
+        done = n4 * 4;
+    }
+    if (done < n) hipLaunchKernelGGL(k_copy_u32, dim3(blocks), dim3(256), 0, s, in, out, done, n);
+    return hipGetLastError();
+}
+
+}  // namespace mms

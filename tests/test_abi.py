@@ -1,0 +1,147 @@
+"""The C ABI on the CPU: the library loads, exports what include/mms.h
+declares, plans as §6.2 prescribes, and rejects bad arguments before any
+device work (no GPU is touched by these tests)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_1702_07961_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mms.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1702_07961_amd import build
+        build.build()
+    return _lib.lib()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mms_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_matches_binding_list():
+    assert header_functions() == sorted(_lib.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_error_string(lib):
+    assert lib.mms_version() >= 100
+    assert isinstance(lib.mms_last_error(), bytes)
+
+
+def expected_rounds(n, T, K):
+    """§6.2: ceil(log_K(ceil(n/T))) merge rounds, computed with integers."""
+    runs = -(-n // T)
+    r = 0
+    while runs > 1:
+        runs = -(-runs // K)
+        r += 1
+    return r
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_plan_pass_count(lib, pairs):
+    p0 = _lib.MmsPlan()
+    assert lib.mms_plan(1, _lib.MMS_PAIRS if pairs else 0, p0) == 0
+    T, K = p0.tile, p0.fanout
+    assert T == 64 * 8 * 4 and K == 16
+    for n in [1, 2, T - 1, T, T + 1, T * K, T * K + 1, T * K * K, T * K * K + 7, 10**8, 2**27, 2**32 - 1]:
+        p = _lib.MmsPlan()
+        assert lib.mms_plan(n, _lib.MMS_PAIRS if pairs else 0, p) == 0
+        assert p.rounds == expected_rounds(n, T, K), n
+        assert p.passes == 1 + p.rounds
+        # ceil(log_K(ceil(n/T))) by floating point, away from exact powers
+        if n > T and math.log(-(-n // T), K) % 1 > 1e-9:
+            assert p.rounds == math.ceil(math.log(-(-n // T), K))
+        ws = lib.mms_workspace_bytes(n, _lib.MMS_PAIRS if pairs else 0)
+        assert ws == p.workspace_bytes
+        if p.rounds:
+            assert ws >= n * 4 * (2 if pairs else 1)
+        else:
+            assert ws == 0
+
+
+def test_plan_headline_size(lib):
+    p = _lib.MmsPlan()
+    assert lib.mms_plan(10**8, 0, p) == 0
+    assert (p.rounds, p.passes) == (4, 5)
+
+
+def test_plan_rejects(lib):
+    p = _lib.MmsPlan()
+    assert lib.mms_plan(1 << 32, 0, p) == _lib.MMS_EINVAL
+    assert b"2^32" in lib.mms_last_error()
+    assert lib.mms_plan(5, 0x80, p) == _lib.MMS_EINVAL
+    assert lib.mms_plan(5, 0, None) == _lib.MMS_EINVAL
+    assert lib.mms_workspace_bytes(0, 0) == 0
+
+
+FAKE = 0x7F0000000000   # never dereferenced: every call below fails its checks first
+
+
+def test_sort_argument_errors(lib):
+    n = 100_000
+    ws = lib.mms_workspace_bytes(n, 0)
+    assert lib.mms_sort_u32(FAKE, FAKE + 4, n, FAKE + 2**30, ws, 0, None) == _lib.MMS_EINVAL
+    assert b"overlap" in lib.mms_last_error()
+    assert lib.mms_sort_u32(None, FAKE, n, FAKE + 2**30, ws, 0, None) == _lib.MMS_EINVAL
+    assert lib.mms_sort_u32(FAKE, FAKE + 2**28, 1 << 32, FAKE + 2**30, ws, 0, None) == _lib.MMS_EINVAL
+    assert lib.mms_sort_u32(FAKE, FAKE + 2**28, n, FAKE + 2**30, ws - 1, 0, None) == _lib.MMS_EINVAL
+    assert b"too small" in lib.mms_last_error()
+    assert lib.mms_sort_u32(FAKE, FAKE + 2**28, n, FAKE + 2**30 + 4, ws, 0, None) == _lib.MMS_EINVAL
+    assert b"aligned" in lib.mms_last_error()
+    assert lib.mms_sort_u32(FAKE, FAKE + 2**28, n, FAKE + 2**28, ws, 0, None) == _lib.MMS_EINVAL
+    assert lib.mms_sort_u32(FAKE, FAKE + 2**28, n, None, 0, 0, None) == _lib.MMS_EINVAL
+    assert lib.mms_sort_u32(FAKE, FAKE + 2**28, n, FAKE + 2**30, ws, 0x40, None) == _lib.MMS_EINVAL
+    assert lib.mms_sort_u32(FAKE, FAKE + 2**28, n, FAKE + 2**30, ws, _lib.MMS_PAIRS, None) == _lib.MMS_EINVAL
+    assert lib.mms_sort_u32(FAKE, FAKE, 0, None, 0, 0, None) == _lib.MMS_OK
+
+
+def test_pairs_argument_errors(lib):
+    n = 100_000
+    ws = lib.mms_workspace_bytes(n, _lib.MMS_PAIRS)
+    K, V, KO, VO, W = FAKE, FAKE + 2**26, FAKE + 2**27, FAKE + 3 * 2**26, FAKE + 2**30
+    assert lib.mms_sort_pairs_u32(K, V, KO, VO, n, W, ws - 256, 0, None) == _lib.MMS_EINVAL
+    assert lib.mms_sort_pairs_u32(K, None, KO, VO, n, W, ws, 0, None) == _lib.MMS_EINVAL
+    assert lib.mms_sort_pairs_u32(K, K + 8, KO, VO, n, W, ws, 0, None) == _lib.MMS_EINVAL
+    assert lib.mms_sort_pairs_u32(K, V, KO, KO, n, W, ws, 0, None) == _lib.MMS_EINVAL
+
+
+def test_partition_argument_errors(lib):
+    assert lib.mms_partition_u32(FAKE, 100, 10, 0, FAKE, FAKE, 1, FAKE, 0, None) == _lib.MMS_EINVAL
+    assert lib.mms_partition_u32(FAKE, 100, 10, 17, FAKE, FAKE, 1, FAKE, 0, None) == _lib.MMS_EINVAL
+    assert lib.mms_partition_u32(FAKE, 100, 0, 4, FAKE, FAKE, 1, FAKE, 0, None) == _lib.MMS_EINVAL
+    assert lib.mms_partition_u32(FAKE, 100, 10, 4, FAKE, FAKE, 0, FAKE, 0, None) == _lib.MMS_OK
+
+
+def test_copy_argument_errors(lib):
+    assert lib.mms_copy_u32(FAKE, FAKE + 8, 100, None) == _lib.MMS_EINVAL
+    assert lib.mms_copy_u32(FAKE, FAKE, 0, None) == _lib.MMS_OK
+
+
+def test_last_error_is_per_thread(lib):
+    import threading
+    lib.mms_plan(1 << 33, 0, _lib.MmsPlan())
+    seen = {}
+
+    def other():
+        seen["msg"] = lib.mms_last_error()
+
+    t = threading.Thread(target=other)
+    t.start()
+    t.join()
+    assert seen["msg"] == b""
+    assert lib.mms_last_error() != b""

@@ -1,0 +1,120 @@
+"""Full-size GPU checks in the launch configuration the benchmark times.
+
+At 10^8 keys and 2^27 pairs the whole oracle sort takes too long for a
+test, so the GPU result is checked by properties that hold at any size —
+sortedness, equality of the key multiset (histogram of the input vs the
+output), stability — by closed forms of the input families (nearly-sorted
+and stride-64 inputs sort to 0..n-1; stride-64 values follow the inverse
+interleave), and at sampled positions against order statistics the oracle
+computes one by one by counting.
+"""
+import numpy as np
+import pytest
+
+import mmsgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+N_KEYS = 10**8
+N_PAIRS = 2**27
+
+
+@pytest.fixture(scope="module")
+def mms():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1702_07961_amd as m
+    m._lib.lib()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+def sample_positions(n, seed, count=6):
+    rng = np.random.default_rng(seed)
+    return sorted({0, n - 1, n // 2, *rng.integers(0, n, count).tolist()})
+
+
+def check_sorted_permutation(x_dev, out_dev, signed=False):
+    a = out_dev.to(torch.int64)
+    if not signed:
+        a = a & 0xFFFFFFFF
+    assert bool((a[1:] >= a[:-1]).all())
+    # same multiset: per-key counts of the input equal those of the output
+    xs = torch.sort(x_dev.to(torch.int64) & 0xFFFFFFFF).values
+    os_ = torch.sort(out_dev.to(torch.int64) & 0xFFFFFFFF).values
+    assert torch.equal(xs, os_)
+
+
+def test_headline_uniform_u32(mms):
+    x = mmsgen.uniform_u32(mmsgen.seed_for(2, 0), N_KEYS)
+    xd = dev(x)
+    out = mms.sort(xd, i32=False)
+    torch.cuda.synchronize()
+    check_sorted_permutation(xd, out)
+    got = out.cpu().numpy().view(np.uint32)
+    for i in sample_positions(N_KEYS, 1, count=4):
+        key, _ = oracle.select(x, i)
+        assert int(got[i]) == key, i
+
+
+@pytest.mark.parametrize("swaps", [0, 10**3, 10**6, 10**8])
+def test_nearly_sorted_int32(mms, swaps):
+    x = mmsgen.nearly_sorted_u32(mmsgen.seed_for(2, 1), N_KEYS, swaps)
+    out = mms.sort(dev(x), i32=True)
+    assert torch.equal(out, torch.arange(N_KEYS, dtype=torch.int32, device="cuda"))
+
+
+def test_uniform_int32_sampled(mms):
+    x = mmsgen.uniform_u32(mmsgen.seed_for(2, 2), N_KEYS)
+    xd = dev(x)
+    out = mms.sort(xd, i32=True)
+    check_sorted_permutation(xd, out, signed=True)
+    got = out.cpu().numpy().view(np.uint32)
+    for i in sample_positions(N_KEYS, 2, count=3):
+        key, _ = oracle.select(x, i, i32=True)
+        assert int(got[i]) == key, i
+
+
+def test_pairs_stride64_closed_form(mms):
+    x = mmsgen.stride64_u32(N_PAIRS)
+    v = mmsgen.iota_u32(N_PAIRS)
+    k, val = mms.sort_pairs(dev(x), dev(v), i32=False)
+    j = torch.arange(N_PAIRS, dtype=torch.int64, device="cuda")
+    rows = N_PAIRS // 64
+    assert torch.equal(k.to(torch.int64), j)
+    assert torch.equal(val.to(torch.int64), (j % rows) * 64 + j // rows)
+
+
+def test_pairs_sixteen_closed_form(mms):
+    x = mmsgen.sixteen_u32(mmsgen.seed_for(3, 1), N_PAIRS)
+    k, val = mms.sort_pairs(dev(x), dev(mmsgen.iota_u32(N_PAIRS)), i32=False)
+    kk = k.to(torch.int64) & 0xFFFFFFFF
+    assert bool((kk[1:] >= kk[:-1]).all())
+    counts = torch.bincount((dev(x).to(torch.int64) & 0xFFFFFFFF) // 0x11111111, minlength=16)
+    assert torch.equal(torch.bincount(kk // 0x11111111, minlength=16), counts)
+    vv = val.to(torch.int64)
+    same = kk[1:] == kk[:-1]
+    assert bool((vv[1:][same] > vv[:-1][same]).all())          # stable inside each run
+    assert torch.equal(dev(x)[val.to(torch.int64)], k)         # values point at their keys
+
+
+def test_pairs_uniform_sampled(mms):
+    x = mmsgen.uniform_u32(mmsgen.seed_for(3, 0), N_PAIRS)
+    k, val = mms.sort_pairs(dev(x), dev(mmsgen.iota_u32(N_PAIRS)), i32=False)
+    kk = k.to(torch.int64) & 0xFFFFFFFF
+    assert bool((kk[1:] >= kk[:-1]).all())
+    vv = val.to(torch.int64)
+    same = kk[1:] == kk[:-1]
+    assert bool((vv[1:][same] > vv[:-1][same]).all())
+    assert torch.equal(dev(x)[vv], k)
+    assert torch.equal(torch.sort(vv).values, torch.arange(N_PAIRS, device="cuda"))
+    kh, vh = k.cpu().numpy().view(np.uint32), val.cpu().numpy().view(np.uint32)
+    for i in sample_positions(N_PAIRS, 3, count=3):
+        key, idx = oracle.select(x, i)
+        assert (int(kh[i]), int(vh[i])) == (key, idx), i
