@@ -122,6 +122,31 @@ int mms_partition_u32(const uint32_t* d_keys, uint64_t n, uint64_t run_len, uint
  */
 int mms_copy_u32(const uint32_t* d_in, uint32_t* d_out, uint64_t n, void* stream);
 
+/*
+ * Per-kernel timing, for measurement harnesses.  While enabled, every kernel
+ * the library launches is bracketed by two hipEvents recorded on the stream
+ * it is launched on, and mms_timing_read() waits for those events and
+ * returns, per kernel kind, the number of launches and their summed
+ * durations since the last reset.  Enabling costs two event records per
+ * launch.  The state is process-wide; calls are thread-safe.
+ */
+typedef enum {
+    MMS_KERNEL_TILE_SORT = 0,  /* base case (§4.3)          */
+    MMS_KERNEL_PARTITION = 1,  /* split indices (§4.1)      */
+    MMS_KERNEL_MERGE = 2,      /* K-way merge (§4.2)        */
+    MMS_KERNEL_COPY = 3,       /* bandwidth probe           */
+    MMS_KERNEL_KINDS = 4
+} mms_kernel_kind;
+
+typedef struct {
+    uint64_t launches[MMS_KERNEL_KINDS];
+    double total_ms[MMS_KERNEL_KINDS];
+} mms_timing_t;
+
+int mms_timing_enable(int on);
+int mms_timing_reset(void);
+int mms_timing_read(mms_timing_t* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,7 +10,8 @@ from __future__ import annotations
 from . import _lib
 from ._lib import MMS_KEY_I32, MMS_PAIRS, MmsError, MmsPlan  # noqa: F401
 
-__all__ = ["sort", "sort_pairs", "partition", "copy", "plan", "workspace_bytes", "MmsError"]
+__all__ = ["sort", "sort_pairs", "partition", "copy", "plan", "workspace_bytes", "MmsError",
+           "timing_enable", "timing_reset", "timing_read"]
 
 
 def _torch():
@@ -125,3 +126,19 @@ def copy(src, dst, stream=None):
     _lib.check(_lib.lib().mms_copy_u32(src.data_ptr(), dst.data_ptr(), src.numel(),
                                        _stream_ptr(stream)))
     return dst
+
+
+def timing_enable(on: bool = True):
+    """Bracket every library kernel launch with HIP events on its stream."""
+    _lib.check(_lib.lib().mms_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    _lib.check(_lib.lib().mms_timing_reset())
+
+
+def timing_read() -> dict:
+    """{kind: (launches, total_ms)} since the last reset; waits for the events."""
+    t = _lib.MmsTiming()
+    _lib.check(_lib.lib().mms_timing_read(t))
+    return {k: (int(t.launches[i]), float(t.total_ms[i])) for i, k in enumerate(_lib.KERNEL_KINDS)}

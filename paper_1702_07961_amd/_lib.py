@@ -26,8 +26,11 @@ MMS_KEY_I32 = 0x2
 # every symbol include/mms.h declares
 EXPORTS = [
     "mms_last_error", "mms_version", "mms_plan", "mms_workspace_bytes", "mms_sort_u32",
-    "mms_sort_pairs_u32", "mms_partition_u32", "mms_copy_u32",
+    "mms_sort_pairs_u32", "mms_partition_u32", "mms_copy_u32", "mms_timing_enable",
+    "mms_timing_reset", "mms_timing_read",
 ]
+
+KERNEL_KINDS = ["tile_sort", "partition", "merge", "copy"]
 
 _vp = ctypes.c_void_p
 _u64 = ctypes.c_uint64
@@ -45,6 +48,13 @@ class MmsPlan(ctypes.Structure):
         ("rounds", ctypes.c_uint32),
         ("passes", ctypes.c_uint32),
         ("workspace_bytes", ctypes.c_uint64),
+    ]
+
+
+class MmsTiming(ctypes.Structure):
+    _fields_ = [
+        ("launches", ctypes.c_uint64 * 4),
+        ("total_ms", ctypes.c_double * 4),
     ]
 
 
@@ -73,6 +83,12 @@ def _declare(lib):
     lib.mms_partition_u32.restype = ctypes.c_int
     lib.mms_copy_u32.argtypes = [_vp, _vp, _u64, _vp]
     lib.mms_copy_u32.restype = ctypes.c_int
+    lib.mms_timing_enable.argtypes = [ctypes.c_int]
+    lib.mms_timing_enable.restype = ctypes.c_int
+    lib.mms_timing_reset.argtypes = []
+    lib.mms_timing_reset.restype = ctypes.c_int
+    lib.mms_timing_read.argtypes = [ctypes.POINTER(MmsTiming)]
+    lib.mms_timing_read.restype = ctypes.c_int
     return lib
 
 

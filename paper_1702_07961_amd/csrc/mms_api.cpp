@@ -6,7 +6,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "mms.h"
 #include "mms_internal.h"
@@ -28,6 +30,52 @@ int fail(int code, const char* fmt, ...) {
 int hip_fail(hipError_t e, const char* what) {
     return fail(MMS_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+// ---- per-kernel timing (mms_timing_*) --------------------------------------
+struct TimingRec {
+    int kind;
+    hipEvent_t a, b;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimingRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+uint64_t g_launch[MMS_KERNEL_KINDS];
+double g_ms[MMS_KERNEL_KINDS];
+
+hipEvent_t take_event() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one kernel launch with events on its stream when timing is on.
+class Timed {
+  public:
+    Timed(int kind, hipStream_t s) : kind_(kind), s_(s) {
+        std::lock_guard<std::mutex> g(g_tmu);
+        if (!g_timing) return;
+        a_ = take_event();
+        b_ = take_event();
+        if (a_ && b_) hipEventRecord(a_, s_);
+    }
+    ~Timed() {
+        if (!a_ || !b_) return;
+        hipEventRecord(b_, s_);
+        std::lock_guard<std::mutex> g(g_tmu);
+        g_recs.push_back({kind_, a_, b_});
+    }
+
+  private:
+    int kind_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
 
 constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -114,16 +162,26 @@ int sort_impl(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t
     auto buf_k = [&](uint32_t i) { return ((p.rounds - i) % 2 == 0) ? kout : ws_k; };
     auto buf_v = [&](uint32_t i) { return ((p.rounds - i) % 2 == 0) ? vout : ws_v; };
 
-    hipError_t e = mms::launch_tile_sort(pairs, kin, vin, buf_k(0), pairs ? buf_v(0) : nullptr, n, flip,
-                                         p.rounds == 0 ? flip : 0u, s);
+    hipError_t e;
+    {
+        Timed tm(MMS_KERNEL_TILE_SORT, s);
+        e = mms::launch_tile_sort(pairs, kin, vin, buf_k(0), pairs ? buf_v(0) : nullptr, n, flip,
+                                  p.rounds == 0 ? flip : 0u, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "tile sort launch");
     uint64_t L = p.T;
     for (uint32_t r = 0; r < p.rounds; ++r, L *= p.K) {
         const mms::RoundGeom g = mms::round_geom(n, L, p.K, p.Tout);
-        e = mms::launch_corank_tiles(buf_k(r), g, table, s);
+        {
+            Timed tm(MMS_KERNEL_PARTITION, s);
+            e = mms::launch_corank_tiles(buf_k(r), g, table, s);
+        }
         if (e != hipSuccess) return hip_fail(e, "partition launch");
-        e = mms::launch_merge(pairs, buf_k(r), pairs ? buf_v(r) : nullptr, buf_k(r + 1),
-                              pairs ? buf_v(r + 1) : nullptr, g, table, r + 1 == p.rounds ? flip : 0u, s);
+        {
+            Timed tm(MMS_KERNEL_MERGE, s);
+            e = mms::launch_merge(pairs, buf_k(r), pairs ? buf_v(r) : nullptr, buf_k(r + 1),
+                                  pairs ? buf_v(r + 1) : nullptr, g, table, r + 1 == p.rounds ? flip : 0u, s);
+        }
         if (e != hipSuccess) return hip_fail(e, "merge launch");
     }
     return MMS_OK;
@@ -181,8 +239,12 @@ int mms_partition_u32(const uint32_t* d_keys, uint64_t n, uint64_t run_len, uint
     if (!d_keys && n) return fail(MMS_EINVAL, "null keys");
     if (!d_group || !d_rank || !d_split) return fail(MMS_EINVAL, "null query or output pointer");
     const uint32_t flip = (flags & MMS_KEY_I32) ? 0x80000000u : 0u;
-    hipError_t e = mms::launch_corank_queries(d_keys, n, run_len, K, d_group, d_rank, nqueries, d_split, flip,
-                                              (hipStream_t)stream);
+    hipError_t e;
+    {
+        Timed tm(MMS_KERNEL_PARTITION, (hipStream_t)stream);
+        e = mms::launch_corank_queries(d_keys, n, run_len, K, d_group, d_rank, nqueries, d_split, flip,
+                                       (hipStream_t)stream);
+    }
     if (e != hipSuccess) return hip_fail(e, "partition launch");
     return MMS_OK;
 }
@@ -191,8 +253,55 @@ int mms_copy_u32(const uint32_t* d_in, uint32_t* d_out, uint64_t n, void* stream
     if (n == 0) return MMS_OK;
     if (!d_in || !d_out) return fail(MMS_EINVAL, "null pointer");
     if (overlaps(d_in, n * 4, d_out, n * 4)) return fail(MMS_EINVAL, "copy buffers overlap");
-    hipError_t e = mms::launch_copy(d_in, d_out, n, (hipStream_t)stream);
+    hipError_t e;
+    {
+        Timed tm(MMS_KERNEL_COPY, (hipStream_t)stream);
+        e = mms::launch_copy(d_in, d_out, n, (hipStream_t)stream);
+    }
     if (e != hipSuccess) return hip_fail(e, "copy launch");
+    return MMS_OK;
+}
+
+int mms_timing_enable(int on) {
+    std::lock_guard<std::mutex> g(g_tmu);
+    g_timing = on != 0;
+    return MMS_OK;
+}
+
+int mms_timing_reset(void) {
+    std::lock_guard<std::mutex> g(g_tmu);
+    for (auto& r : g_recs) {
+        hipEventSynchronize(r.b);
+        g_pool.push_back(r.a);
+        g_pool.push_back(r.b);
+    }
+    g_recs.clear();
+    for (int k = 0; k < MMS_KERNEL_KINDS; ++k) {
+        g_launch[k] = 0;
+        g_ms[k] = 0.0;
+    }
+    return MMS_OK;
+}
+
+int mms_timing_read(mms_timing_t* out) {
+    if (!out) return fail(MMS_EINVAL, "null timing pointer");
+    std::lock_guard<std::mutex> g(g_tmu);
+    for (auto& r : g_recs) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return hip_fail(e, "timing event");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return hip_fail(e, "timing event");
+        g_launch[r.kind] += 1;
+        g_ms[r.kind] += ms;
+        g_pool.push_back(r.a);
+        g_pool.push_back(r.b);
+    }
+    g_recs.clear();
+    for (int k = 0; k < MMS_KERNEL_KINDS; ++k) {
+        out->launches[k] = g_launch[k];
+        out->total_ms[k] = g_ms[k];
+    }
     return MMS_OK;
 }
 
