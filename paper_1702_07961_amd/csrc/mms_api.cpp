@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -77,6 +78,36 @@ class Timed {
     hipEvent_t a_ = nullptr, b_ = nullptr;
 };
 
+// One resident workgroup per compute unit for the persistent merge kernel.
+unsigned persistent_grid() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+    return (unsigned)cus;
+}
+
+// Merge kernel shape; MMS_MERGE_VARIANT=1 selects 16 waves with 512-key blocks.
+int merge_variant() {
+    static const int v = [] {
+        const char* s = getenv("MMS_MERGE_VARIANT");
+        return s ? atoi(s) : 0;
+    }();
+    return v;
+}
+
+// Output tile of the keys-only merge; MMS_TOUT overrides (multiple of 256,
+// at most the compiled maximum).
+uint32_t keys_merge_tile() {
+    static const uint32_t v = [] {
+        const char* s = getenv("MMS_TOUT");
+        uint32_t t = s ? (uint32_t)atoi(s) : mms::kToutKeys;
+        if (t < 1024 || t > mms::kToutKeys || t % 256) t = mms::kToutKeys;
+        return t;
+    }();
+    return v;
+}
+
 constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -100,7 +131,7 @@ Plan make_plan(uint64_t n, uint32_t flags) {
     p.pairs = (flags & MMS_PAIRS) != 0;
     p.T = mms::kT1;
     p.K = mms::kMaxFanout;
-    p.Tout = p.pairs ? mms::kToutPairs : mms::kToutKeys;
+    p.Tout = p.pairs ? mms::kToutPairs : keys_merge_tile();
     p.rounds = 0;
     p.max_tiles = 0;
     for (uint64_t L = p.T; L < n; L *= p.K) {
@@ -179,8 +210,12 @@ int sort_impl(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t
         if (e != hipSuccess) return hip_fail(e, "partition launch");
         {
             Timed tm(MMS_KERNEL_MERGE, s);
-            e = mms::launch_merge(pairs, buf_k(r), pairs ? buf_v(r) : nullptr, buf_k(r + 1),
-                                  pairs ? buf_v(r + 1) : nullptr, g, table, r + 1 == p.rounds ? flip : 0u, s);
+            if (pairs)
+                e = mms::launch_merge(true, buf_k(r), buf_v(r), buf_k(r + 1), buf_v(r + 1), g, table,
+                                      r + 1 == p.rounds ? flip : 0u, s);
+            else
+                e = mms::launch_merge_keys(buf_k(r), buf_k(r + 1), g, table, r + 1 == p.rounds ? flip : 0u,
+                                           persistent_grid(), merge_variant(), s);
         }
         if (e != hipSuccess) return hip_fail(e, "merge launch");
     }

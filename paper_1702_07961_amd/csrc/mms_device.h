@@ -161,13 +161,16 @@ __device__ __forceinline__ uint32_t lds_corank2(const uint32_t* Xk, uint32_t aA,
     uint32_t lo = d > lb ? d - lb : 0u;
     uint32_t hi = min(d, la);
     while (lo < hi) {
+        // 128 probes per round: probe q = lane + 64*j sits at lo + q*step
         const uint32_t R = hi - lo;
-        const uint32_t step = ((R + 63u) >> 6) | 1u;
-        const uint32_t m = lo + (uint32_t)lane * step;
-        bool pred = false;
-        if (m < hi) pred = Xk[aA + m] <= Xk[aB + d - 1u - m];
-        const uint32_t t = (uint32_t)__popcll(__ballot(pred));
-        const uint32_t nvalid = min(64u, (R + step - 1u) / step);
+        const uint32_t step = ((R + 127u) >> 7) | 1u;
+        const uint32_t m0 = lo + (uint32_t)lane * step;
+        const uint32_t m1 = m0 + 64u * step;
+        bool p0 = false, p1 = false;
+        if (m0 < hi) p0 = Xk[aA + m0] <= Xk[aB + d - 1u - m0];
+        if (m1 < hi) p1 = Xk[aA + m1] <= Xk[aB + d - 1u - m1];
+        const uint32_t t = (uint32_t)__popcll(__ballot(p0)) + (uint32_t)__popcll(__ballot(p1));
+        const uint32_t nvalid = min(128u, (R + step - 1u) / step);
         const uint32_t nlo = t > 0 ? lo + (t - 1u) * step + 1u : lo;
         const uint32_t nhi = t < nvalid ? lo + t * step : hi;
         lo = nlo;
@@ -254,8 +257,9 @@ template <int EM, bool P, class Sink>
 __device__ __forceinline__ void merge_level(const uint32_t* Xk, const uint32_t* Xv, const uint32_t* seg0,
                                             uint32_t nseg0, uint32_t lvl, uint32_t total, const Sink& out,
                                             int wave, int nwaves, int lane) {
-    const uint32_t o0 = (uint32_t)(((uint64_t)total * (uint32_t)wave) / (uint32_t)nwaves);
-    const uint32_t o1 = (uint32_t)(((uint64_t)total * (uint32_t)(wave + 1)) / (uint32_t)nwaves);
+    // total < 2^20 here, so the 32-bit products cannot overflow
+    const uint32_t o0 = total * (uint32_t)wave / (uint32_t)nwaves;
+    const uint32_t o1 = total * (uint32_t)(wave + 1) / (uint32_t)nwaves;
     const uint32_t nseg = (nseg0 + (1u << lvl) - 1u) >> lvl;
     const uint32_t npairs = (nseg + 1u) / 2u;
     for (uint32_t i = 0; i < npairs; ++i) {
@@ -265,6 +269,248 @@ __device__ __forceinline__ void merge_level(const uint32_t* Xk, const uint32_t* 
         const uint32_t lo = max(o0, s0), hi = min(o1, s2);
         if (lo >= hi) continue;
         merge_pair_range<EM, P>(Xk, Xv, s0, s1 - s0, s1, s2 - s1, lo - s0, hi - s0, out, s0, lane);
+    }
+}
+
+// ===========================================================================
+// Keys-only block merge with LDS transposes.
+//
+// The bitonic block of N = 64*EM keys is sorted with every compare-exchange
+// inside a lane.  Index bits are moved between register and lane positions
+// by two transposes through a wave-private scratch whose 64-word rows are
+// padded (row stride RS), which makes every scratch access conflict-free:
+//   S  (as read)   register = index bits above 6, lane = bits 5..0
+//   T1             register = bits 5..2 (EM=16) or 5..3 (EM=8)
+//   F  (as stored) register 4c+j = position c*256 + 4*lane + j, so each
+//                  lane stores 16-byte chunks and a wave stores 1 KiB runs
+// With EM = 8 index bit 2 is lane bit 0 in F and takes one DPP exchange.
+// Measured gfx950 rules behind the padding: 32-bit accesses are served 32
+// lanes per cycle over 32 banks, 128-bit accesses 16 lanes per cycle over 64
+// banks.
+// ===========================================================================
+template <int EM> struct Xpose;
+template <> struct Xpose<16> {
+    static constexpr uint32_t RS = 68;
+    static constexpr uint32_t WORDS = 16 * RS;
+};
+template <> struct Xpose<8> {
+    static constexpr uint32_t RS = 72;
+    static constexpr uint32_t WORDS = 8 * RS;
+};
+
+// compiler and LDS ordering point for a wave's own scratch traffic
+__device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+__device__ __forceinline__ void cex_u32(uint32_t& lo, uint32_t& hi) {
+    const uint32_t a = lo, b = hi;
+    lo = min(a, b);
+    hi = max(a, b);
+}
+
+template <int EM>
+__device__ __forceinline__ void reg_stages(uint32_t (&m)[EM]) {
+#pragma unroll
+    for (int d = EM / 2; d >= 1; d >>= 1) {
+#pragma unroll
+        for (int e = 0; e < EM; ++e)
+            if ((e & d) == 0) cex_u32(m[e], m[e | d]);
+    }
+}
+
+// Sort the bitonic block held in layout S; the result is left in layout F.
+template <int EM>
+__device__ __forceinline__ void block_sort_keys(uint32_t (&m)[EM], uint32_t* scr, int lane) {
+    constexpr uint32_t RS = Xpose<EM>::RS;
+    const uint32_t ul = (uint32_t)lane;
+    asm volatile("" ::: "memory");                       // keep the previous block's scratch reads first
+    reg_stages<EM>(m);                                   // index bits 9..6 (EM=16) / 8..6 (EM=8)
+#pragma unroll
+    for (int e = 0; e < EM; ++e) scr[e * RS + ul] = m[e];
+    lds_wave_sync();
+    uint32_t tb;
+    if constexpr (EM == 16) tb = (ul >> 2) * RS + (ul & 3u);   // lane = (bits 9..6, bits 1..0)
+    else tb = (ul >> 3) * RS + (ul & 7u);                       // lane = (bits 8..6, bits 2..0)
+    constexpr uint32_t CS = EM == 16 ? 4u : 8u;                 // stride of the register bits
+#pragma unroll
+    for (int e = 0; e < EM; ++e) m[e] = scr[tb + e * CS];
+    reg_stages<EM>(m);                                   // index bits 5..2 / 5..3
+#pragma unroll
+    for (int e = 0; e < EM; ++e) scr[tb + e * CS] = m[e];
+    lds_wave_sync();
+    const uint32_t fb = (ul >> 4) * RS + 4u * (ul & 15u);
+#pragma unroll
+    for (int c = 0; c < EM / 4; ++c) {
+        const uint4 v = *reinterpret_cast<const uint4*>(scr + fb + (uint32_t)c * 4u * RS);
+        m[4 * c + 0] = v.x;
+        m[4 * c + 1] = v.y;
+        m[4 * c + 2] = v.z;
+        m[4 * c + 3] = v.w;
+    }
+    if constexpr (EM == 8) {                             // index bit 2 = lane bit 0
+        const bool hi_lane = (ul & 1u) != 0;
+#pragma unroll
+        for (int e = 0; e < EM; ++e) {
+            const uint32_t o = (uint32_t)__builtin_amdgcn_mov_dpp((int)m[e], 0xB1, 0xF, 0xF, false);
+            m[e] = hi_lane ? max(m[e], o) : min(m[e], o);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < EM / 4; ++c) {                   // index bits 1..0
+        cex_u32(m[4 * c + 0], m[4 * c + 2]);
+        cex_u32(m[4 * c + 1], m[4 * c + 3]);
+        cex_u32(m[4 * c + 0], m[4 * c + 1]);
+        cex_u32(m[4 * c + 2], m[4 * c + 3]);
+    }
+}
+
+// Sinks for a sorted block in layout F: block position t = c*256 + 4*lane + j
+// goes to pos0 + t when t < cnt.  pos0 must be a multiple of 4 for the
+// 16-byte path; `vec` says whether the base pointer allows it.
+struct LdsSinkKeys {
+    uint32_t* y;
+    template <int EM>
+    __device__ __forceinline__ void put_block(uint32_t pos0, uint32_t cnt, const uint32_t (&m)[EM], int lane) const {
+#pragma unroll
+        for (int c = 0; c < EM / 4; ++c) {
+            const uint32_t t = (uint32_t)c * 256u + 4u * (uint32_t)lane;
+            if (t + 4u <= cnt) {
+                *reinterpret_cast<uint4*>(y + pos0 + t) = make_uint4(m[4 * c], m[4 * c + 1], m[4 * c + 2], m[4 * c + 3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (t + (uint32_t)j < cnt) y[pos0 + t + j] = m[4 * c + j];
+            }
+        }
+    }
+};
+struct GlobalSinkKeys {
+    uint32_t* y;     // tile output base
+    uint32_t flip;
+    uint32_t lim;    // positions >= lim are not stored
+    bool vec;        // y is 16-byte aligned
+    template <int EM>
+    __device__ __forceinline__ void put_block(uint32_t pos0, uint32_t cnt, const uint32_t (&m)[EM], int lane) const {
+        const uint32_t c_lim = min(cnt, lim > pos0 ? lim - pos0 : 0u);
+#pragma unroll
+        for (int c = 0; c < EM / 4; ++c) {
+            const uint32_t t = (uint32_t)c * 256u + 4u * (uint32_t)lane;
+            if (vec && t + 4u <= c_lim) {
+                *reinterpret_cast<uint4*>(y + pos0 + t) =
+                    make_uint4(m[4 * c] ^ flip, m[4 * c + 1] ^ flip, m[4 * c + 2] ^ flip, m[4 * c + 3] ^ flip);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (t + (uint32_t)j < c_lim) y[pos0 + t + j] = m[4 * c + j] ^ flip;
+            }
+        }
+    }
+};
+
+// Merge outputs [d0, d1) of A = X[aA, aA+la) and B = X[aB, aB+lb) (keys),
+// blocks of N = 64*EM as in merge_pair_range; out_base + d0 must be a
+// multiple of 4.
+template <int EM, class Sink>
+__device__ __forceinline__ void merge_pair_range_keys(const uint32_t* X, uint32_t aA, uint32_t la, uint32_t aB,
+                                                      uint32_t lb, uint32_t d0, uint32_t d1, const Sink& out,
+                                                      uint32_t out_base, uint32_t* scr, int lane) {
+    constexpr uint32_t N = (uint32_t)kWave * EM;
+    uint32_t p = lds_corank2(X, aA, la, aB, lb, d0, lane);
+    uint32_t q = d0 - p;
+    for (uint32_t o = d0; o < d1; o += N) {
+        uint32_t m[EM];
+        uint32_t u = 0;
+        if (p + N <= la && q + N <= lb) {
+            const uint32_t* Ap = X + aA + p + (uint32_t)lane;
+            const uint32_t* Bp = X + aB + q + (N - 1u) - (uint32_t)lane;
+#pragma unroll
+            for (int e = 0; e < EM; ++e) {
+                const uint32_t a = Ap[e * kWave];
+                const uint32_t b = Bp[-(e * kWave)];
+                m[e] = min(a, b);
+                u += (uint32_t)__popcll(__ballot(a <= b));
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < EM; ++e) {
+                const uint32_t k = (uint32_t)e * kWave + (uint32_t)lane;
+                const uint32_t ia = p + k;
+                const uint32_t jb = q + (N - 1u - k);
+                const uint32_t a = ia < la ? X[aA + ia] : kSentKey;
+                const uint32_t b = jb < lb ? X[aB + jb] : kSentKey;
+                m[e] = min(a, b);
+                u += (uint32_t)__popcll(__ballot(a <= b));
+            }
+        }
+        block_sort_keys<EM>(m, scr, lane);
+        out.template put_block<EM>(out_base + o, min(N, d1 - o), m, lane);
+        p += u;
+        q += N - u;
+    }
+}
+
+// One merge level over segments with 4-aligned starts: level-lvl segment i
+// starts at sbeg[i<<lvl] and holds plen[(i+1)<<lvl] - plen[i<<lvl] keys
+// (indices clamped to nseg0).  Waves split the physical range [0,
+// sbeg[nseg0]) at multiples of 4.
+//
+// Waves are shared out between the level's pairs in proportion to the
+// pairs' sizes: wave w belongs to the pair holding the midpoint of its
+// equal share of the level, and a pair's waves split it evenly, so a wave
+// normally merges one contiguous range with one split search.  A pair that
+// holds no midpoint goes to the wave whose share contains its start.
+template <int EM, class Sink>
+__device__ __forceinline__ void merge_level_keys(const uint32_t* X, const uint32_t* sbeg, const uint32_t* plen,
+                                                 uint32_t nseg0, uint32_t lvl, const Sink& out, uint32_t* scr,
+                                                 int wave, int nwaves, int lane) {
+    // all quantities below stay under 2^24, so 32-bit division is exact
+    const uint32_t total = plen[nseg0];               // keys in the level (gaps excluded)
+    const uint32_t nseg = (nseg0 + (1u << lvl) - 1u) >> lvl;
+    const uint32_t npairs = (nseg + 1u) / 2u;
+    const uint32_t W = (uint32_t)nwaves;
+    const uint32_t w = (uint32_t)wave;
+    if (total == 0) return;
+    // lane i describes pair i (npairs <= 32); the wave then walks the pairs
+    // with wave-uniform copies of those values
+    uint32_t p_aA = 0, p_aB = 0, p_la = 0, p_lb = 0, p_v0 = 0, p_v1 = 0, p_own = 0;
+    if ((uint32_t)lane < npairs) {
+        const uint32_t i = (uint32_t)lane;
+        const uint32_t g0 = min((2u * i) << lvl, nseg0);
+        const uint32_t g1 = min((2u * i + 1u) << lvl, nseg0);
+        const uint32_t g2 = min((2u * i + 2u) << lvl, nseg0);
+        p_aA = sbeg[g0];
+        p_aB = sbeg[g1];
+        p_la = plen[g1] - plen[g0];
+        p_lb = plen[g2] - plen[g1];
+        // waves whose midpoint (2v+1)*total/(2W) lies in the pair: v in [v0, v1),
+        // v0 = smallest v with (2v+1)*total >= 2*W*plen[g0]
+        const uint32_t n0 = 2u * W * plen[g0], n1 = 2u * W * plen[g2];
+        p_v0 = min(n0 <= total ? 0u : (n0 + total - 1u) / (2u * total), W);
+        p_v1 = min(n1 <= total ? 0u : (n1 + total - 1u) / (2u * total), W);
+        // no midpoint inside: the wave whose equal share holds the pair start
+        p_own = min(plen[g0] * W / total, W - 1u);
+    }
+    for (uint32_t i = 0; i < npairs; ++i) {
+        const uint32_t la = (uint32_t)__builtin_amdgcn_readlane((int)p_la, (int)i);
+        const uint32_t lb = (uint32_t)__builtin_amdgcn_readlane((int)p_lb, (int)i);
+        const uint32_t s = la + lb;
+        if (s == 0) continue;
+        const uint32_t v0 = (uint32_t)__builtin_amdgcn_readlane((int)p_v0, (int)i);
+        const uint32_t v1 = (uint32_t)__builtin_amdgcn_readlane((int)p_v1, (int)i);
+        uint32_t d0, d1;
+        if (v1 > v0) {
+            if (w < v0 || w >= v1) continue;
+            const uint32_t nw = v1 - v0, j = w - v0;
+            d0 = (s * j / nw) & ~3u;
+            d1 = j + 1 == nw ? s : (s * (j + 1) / nw) & ~3u;
+        } else {
+            if (w != (uint32_t)__builtin_amdgcn_readlane((int)p_own, (int)i)) continue;
+            d0 = 0;
+            d1 = s;
+        }
+        if (d0 >= d1) continue;
+        const uint32_t aA = (uint32_t)__builtin_amdgcn_readlane((int)p_aA, (int)i);
+        const uint32_t aB = (uint32_t)__builtin_amdgcn_readlane((int)p_aB, (int)i);
+        merge_pair_range_keys<EM>(X, aA, la, aB, lb, d0, d1, out, aA, scr, lane);
     }
 }
 

@@ -12,7 +12,9 @@ namespace mms {
 constexpr int kE1 = 8;
 constexpr int kW1 = 4;
 constexpr uint32_t kT1 = 64u * kE1 * kW1;
-constexpr int kEM = 8;
+constexpr int kEM = 8;      // merge block of the key-value path
+constexpr int kEM1 = 8;     // merge block of the keys-only base case
+constexpr int kEM3 = 16;    // merge block of the keys-only merge rounds
 constexpr int kW3 = 8;
 constexpr uint32_t kToutKeys = 8192;
 constexpr uint32_t kToutPairs = 4096;
@@ -42,6 +44,14 @@ hipError_t launch_corank_queries(const uint32_t* keys, uint64_t n, uint64_t L, u
 hipError_t launch_merge(bool pairs, const uint32_t* src_k, const uint32_t* src_v, uint32_t* dst_k,
                         uint32_t* dst_v, const RoundGeom& g, const uint32_t* table, uint32_t flip_out,
                         hipStream_t s);
+
+size_t merge_lds_bytes(bool pairs, uint32_t Tout, uint32_t K);
+
+// Keys-only merge round, persistent: `grid` workgroups walk the round's
+// tiles.  variant 0: 64x16-key blocks, 8 waves; variant 1: 64x8-key blocks,
+// 16 waves.
+hipError_t launch_merge_keys(const uint32_t* src, uint32_t* dst, const RoundGeom& g, const uint32_t* table,
+                             uint32_t flip_out, unsigned grid, int variant, hipStream_t s);
 
 hipError_t launch_copy(const uint32_t* in, uint32_t* out, uint64_t n, hipStream_t s);
 

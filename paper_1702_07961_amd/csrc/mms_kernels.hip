@@ -27,12 +27,13 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort(const uint32_t* __restrict
                                                       uint32_t flip_out) {
     constexpr uint32_t CH = 64u * E;
     constexpr uint32_t T = CH * W;
-    extern __shared__ uint32_t smem[];
+    extern __shared__ __align__(16) uint32_t smem[];
     uint32_t* Xk = smem;
     uint32_t* Yk = smem + T;
     uint32_t* Xv = P ? smem + 2 * T : nullptr;
     uint32_t* Yv = P ? smem + 3 * T : nullptr;
-    uint32_t* seg0 = smem + (P ? 4 : 2) * T;
+    uint32_t* seg0 = smem + (P ? 4 : 2) * T;        // [W + 1] run starts (= prefix lengths)
+    uint32_t* scr = seg0 + 32;                       // keys: W wave-private transpose scratches
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -60,14 +61,26 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort(const uint32_t* __restrict
     if (threadIdx.x <= (unsigned)W) seg0[threadIdx.x] = threadIdx.x * CH;
     __syncthreads();
 
+    uint32_t* wscr = scr + (uint32_t)wave * Xpose<kEM1>::WORDS;
+    const bool vec = ((uintptr_t)(out_k + base) & 15u) == 0;
     for (uint32_t lvl = 0; (1u << lvl) < (uint32_t)W; ++lvl) {
         const bool last = (2u << lvl) >= (uint32_t)W;
-        if (last) {
-            GlobalSinkLim<P> out{out_k + base, P ? out_v + base : nullptr, flip_out, cnt};
-            merge_level<kEM, P>(Xk, Xv, seg0, W, lvl, T, out, wave, W, lane);
+        if constexpr (P) {
+            if (last) {
+                GlobalSinkLim<P> out{out_k + base, out_v + base, flip_out, cnt};
+                merge_level<kEM, P>(Xk, Xv, seg0, W, lvl, T, out, wave, W, lane);
+            } else {
+                LdsSink<P> out{Yk, Yv};
+                merge_level<kEM, P>(Xk, Xv, seg0, W, lvl, T, out, wave, W, lane);
+            }
         } else {
-            LdsSink<P> out{Yk, Yv};
-            merge_level<kEM, P>(Xk, Xv, seg0, W, lvl, T, out, wave, W, lane);
+            if (last) {
+                GlobalSinkKeys out{out_k + base, flip_out, cnt, vec};
+                merge_level_keys<kEM1>(Xk, seg0, seg0, W, lvl, out, wscr, wave, W, lane);
+            } else {
+                LdsSinkKeys out{Yk};
+                merge_level_keys<kEM1>(Xk, seg0, seg0, W, lvl, out, wscr, wave, W, lane);
+            }
         }
         __syncthreads();
         uint32_t* t = Xk; Xk = Yk; Yk = t;
@@ -85,11 +98,11 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort(const uint32_t* __restrict
 // smallest such representatives overall (the first r elements are closed
 // downwards).  Their total t_h = sum_k floor(c_k/h) lies in
 // [ceil((r - K(h-1))/h), floor(r/h)], an interval narrower than K.
-// Going from resolution 2h to h, run k can only gain the two half-blocks of
+// Going from resolution 2h to h, run k can only gain half-blocks of the
 // blocks the previous level left undecided; every such candidate is probed
 // once, the candidates are ranked in the wave, and the bounds on t_h turn
 // into bounds [lo_k, hi_k] on floor(c_k/h) whose widths sum to less than K.
-// So at most 4K-2 candidates exist per level (one per lane for K <= 16), and
+// So at most 3K-2 candidates exist per level (one per lane for K <= 16), and
 // at h = 1 the bounds meet: c_k = lo_k = hi_k.  Ties are ordered by (key,
 // run, position), the stable order.
 // ===========================================================================
@@ -99,77 +112,67 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, uint32_t l) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, int lane, uint32_t* total) {
-    uint32_t incl = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)incl, d, 64);
-        if (lane >= d) incl += y;
-    }
-    *total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    return incl - x;
-}
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, d, 64);
-        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), d, 64);
-        x += ((uint64_t)hi << 32) | lo;
-    }
+// Inclusive sum over the 16 lanes of each row (DPP row shifts).
+__device__ __forceinline__ uint32_t row16_incl_sum(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);   // row_shr:8
     return x;
 }
 
-// Returns c_k in lane k (k < Kg); other lanes return 0.  All 64 lanes call.
+// Returns c_k in lane k (k < Kg <= 16); other lanes return 0.  All 64 lanes
+// call.  Resolution h = 2^l is handled with shifts.
 __device__ uint64_t corank_wave(const uint32_t* __restrict__ keys, uint64_t gb, uint64_t glen, uint64_t L,
                                 uint32_t Kg, uint64_t r, uint32_t flip, int lane) {
     const bool own = (uint32_t)lane < Kg;
     const uint64_t nk = own ? min(L, glen - (uint64_t)lane * L) : 0;
     const uint64_t maxlen = Kg > 1 ? L : glen;
-    uint64_t s0 = 1;
-    while (s0 <= maxlen) s0 <<= 1;
-    uint64_t lo = 0, hi = 0;   // bounds on floor(c_k / h), lane k
-    for (uint64_t h = s0 >> 1; h >= 1; h >>= 1) {
-        const uint64_t nb = nk / h;                       // full blocks of run k at resolution h
-        const uint64_t jlo = 2 * lo;
-        const uint64_t jhi = min(2 * hi + 1, nb == 0 ? 0 : nb - 1);
-        const uint32_t cnt = (own && nb > jlo) ? (uint32_t)(jhi - jlo + 1) : 0u;
-        uint32_t total;
-        const uint32_t off = wave_excl_scan(cnt, lane, &total);
+    int lh = 0;
+    while ((1ull << lh) <= maxlen) ++lh;   // first resolution 2^lh exceeds every run
+    uint32_t lo = 0, hi = 0;               // bounds on floor(c_k / 2^(l+1)), lane k
+    for (int l = lh - 1; l >= 0; --l) {
+        const uint32_t nb = (uint32_t)(nk >> l);   // full blocks of run k at resolution 2^l
+        const uint32_t jlo = 2u * lo;
+        // block hi at resolution 2h is never inside (floor(c_k/2h) <= hi), so
+        // its second half 2hi+1 is decided and only [2lo, 2hi] are candidates
+        const uint32_t jhi = min(2u * hi, nb == 0 ? 0u : nb - 1u);
+        const uint32_t cnt = (own && nb > jlo) ? jhi - jlo + 1u : 0u;
+        const uint32_t incl = row16_incl_sum(cnt);
+        const uint32_t off = incl - cnt;
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 15);
 
         // candidate owned by this lane: run kk, block j
         uint32_t kk = 0;
-        for (uint32_t k = 0; k < Kg; ++k)
+        for (uint32_t k = 1; k < Kg; ++k)
             if ((uint32_t)__builtin_amdgcn_readlane((int)off, (int)k) <= (uint32_t)lane) kk = k;
         const bool valid = (uint32_t)lane < total;
         const uint32_t my_off = (uint32_t)__shfl((int)off, (int)kk, 64);
-        const uint64_t my_jlo = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(jlo >> 0), (int)kk, 64)) |
-                                ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(jlo >> 32), (int)kk, 64) << 32);
+        const uint32_t my_jlo = (uint32_t)__shfl((int)jlo, (int)kk, 64);
         const uint32_t local = (uint32_t)lane - my_off;
         uint64_t comp = ~0ull;
         if (valid) {
-            const uint64_t j = my_jlo + local;
-            const uint64_t pos = (j + 1) * h - 1;
+            const uint64_t pos = ((uint64_t)(my_jlo + local + 1u) << l) - 1u;
             const uint32_t key = keys[gb + (uint64_t)kk * L + pos] ^ flip;
             comp = ((uint64_t)key << 32) | ((uint64_t)kk << 8) | (uint64_t)local;
         }
         uint32_t rank = 0;
         for (uint32_t mu = 0; mu < total; ++mu) rank += readlane_u64(comp, mu) < comp ? 1u : 0u;
 
-        const uint64_t sum2lo = wave_sum_u64(own ? 2 * lo : 0);
-        const int64_t slack = (int64_t)Kg * (int64_t)(h - 1);
-        const int64_t num = (int64_t)r - slack;
-        const uint64_t tlo = num > 0 ? ((uint64_t)num + h - 1) / h : 0;
-        const uint64_t thi = r / h;
-        const uint64_t mlo = tlo > sum2lo ? min<uint64_t>(tlo - sum2lo, total) : 0;
-        const uint64_t mhi = thi > sum2lo ? min<uint64_t>(thi - sum2lo, total) : 0;
+        const uint32_t sum2lo = (uint32_t)__builtin_amdgcn_readlane((int)row16_incl_sum(own ? jlo : 0u), 15);
+        const uint64_t hm1 = (1ull << l) - 1u;
+        const int64_t num = (int64_t)r - (int64_t)Kg * (int64_t)hm1;
+        const uint64_t tlo = num > 0 ? ((uint64_t)num + hm1) >> l : 0;
+        const uint64_t thi = r >> l;
+        const uint32_t mlo = tlo > sum2lo ? (uint32_t)min<uint64_t>(tlo - sum2lo, total) : 0u;
+        const uint32_t mhi = thi > sum2lo ? (uint32_t)min<uint64_t>(thi - sum2lo, total) : 0u;
         const uint64_t blo = __ballot(valid && rank < mlo);
         const uint64_t bhi = __ballot(valid && rank < mhi);
         const uint64_t mask = cnt ? (((cnt >= 64 ? ~0ull : ((1ull << cnt) - 1))) << off) : 0ull;
-        const uint64_t nlo = jlo + (uint64_t)__popcll(blo & mask);
-        const uint64_t nhi = jlo + (uint64_t)__popcll(bhi & mask);
-        lo = own ? nlo : 0;
-        hi = own ? nhi : 0;
+        const uint32_t nlo = jlo + (uint32_t)__popcll(blo & mask);
+        const uint32_t nhi = jlo + (uint32_t)__popcll(bhi & mask);
+        lo = own ? nlo : 0u;
+        hi = own ? nhi : 0u;
     }
     return lo;
 }
@@ -332,13 +335,14 @@ static hipError_t allow_lds(const void* f, size_t bytes) {
 hipError_t launch_tile_sort(bool pairs, const uint32_t* in_k, const uint32_t* in_v, uint32_t* out_k,
                             uint32_t* out_v, uint64_t n, uint32_t flip_in, uint32_t flip_out, hipStream_t s) {
     const uint64_t blocks = (n + kT1 - 1) / kT1;
-    const size_t lds = ((pairs ? 4u : 2u) * kT1 + 32u) * sizeof(uint32_t);
     if (pairs) {
+        const size_t lds = (4u * kT1 + 32u) * sizeof(uint32_t);
         hipError_t e = allow_lds((const void*)k_tile_sort<kE1, kW1, true>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_tile_sort<kE1, kW1, true>), dim3((unsigned)blocks), dim3(kW1 * 64), lds, s, in_k, in_v,
                            out_k, out_v, n, flip_in, flip_out);
     } else {
+        const size_t lds = (2u * kT1 + 32u + kW1 * Xpose<kEM1>::WORDS) * sizeof(uint32_t);
         hipError_t e = allow_lds((const void*)k_tile_sort<kE1, kW1, false>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_tile_sort<kE1, kW1, false>), dim3((unsigned)blocks), dim3(kW1 * 64), lds, s, in_k,
@@ -362,19 +366,21 @@ hipError_t launch_corank_queries(const uint32_t* keys, uint64_t n, uint64_t L, u
     return hipGetLastError();
 }
 
+size_t merge_lds_bytes(bool pairs, uint32_t Tout, uint32_t K) {
+    if (pairs) return ((4u * Tout + 2u * kMaxFanout + 8u) * sizeof(uint32_t));
+    return (2u * (Tout + 4u * K) + kW3 * Xpose<kEM3>::WORDS + 3u * (kMaxFanout + 1u)) * sizeof(uint32_t);
+}
+
 hipError_t launch_merge(bool pairs, const uint32_t* src_k, const uint32_t* src_v, uint32_t* dst_k, uint32_t* dst_v,
                         const RoundGeom& g, const uint32_t* table, uint32_t flip_out, hipStream_t s) {
-    const size_t lds = ((pairs ? 4u : 2u) * g.Tout + 2u * kMaxFanout + 8u) * sizeof(uint32_t);
+    const size_t lds = merge_lds_bytes(pairs, g.Tout, g.K);
     if (pairs) {
         hipError_t e = allow_lds((const void*)k_merge<kW3, true>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_merge<kW3, true>), dim3((unsigned)g.tiles), dim3(kW3 * 64), lds, s, src_k, src_v, dst_k,
                            dst_v, g.n, g.L, g.K, g.Tout, g.tiles_per_group, table, flip_out);
     } else {
-        hipError_t e = allow_lds((const void*)k_merge<kW3, false>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_merge<kW3, false>), dim3((unsigned)g.tiles), dim3(kW3 * 64), lds, s, src_k, src_v,
-                           dst_k, dst_v, g.n, g.L, g.K, g.Tout, g.tiles_per_group, table, flip_out);
+        return hipErrorInvalidValue;   // keys use launch_merge_keys
     }
     return hipGetLastError();
 }
