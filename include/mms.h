@@ -123,6 +123,53 @@ int mms_partition_u32(const uint32_t* d_keys, uint64_t n, uint64_t run_len, uint
 int mms_copy_u32(const uint32_t* d_in, uint32_t* d_out, uint64_t n, void* stream);
 
 /*
+ * Batched (segmented) sort: every segment s = [h_offsets[s], h_offsets[s+1])
+ * of the arrays is sorted on its own, exactly as mms_sort_u32 (keys only,
+ * d_vin == d_vout == NULL) or mms_sort_pairs_u32 (stable) would sort it.
+ * h_offsets is a host array of num_segs + 1 non-decreasing element offsets;
+ * elements outside [h_offsets[0], h_offsets[num_segs]) are untouched, and
+ * empty segments are allowed.  Each segment must hold fewer than 2^32
+ * elements.  Buffers follow mms_sort_u32's aliasing rules over the whole
+ * range; d_ws holds mms_segmented_workspace_bytes(...) bytes.
+ *
+ * All segments advance together: one launch per kernel and phase covers
+ * every segment's tiles (the base case, then per round the partition and
+ * the merge).  The first call with a given (offsets, pointers, flags,
+ * tuning) captures those launches into a hipGraph, and later calls with the
+ * same signature replay it with a single graph launch on `stream`.  The
+ * library keeps, per captured signature (up to 8, least recently used
+ * evicted), the per-tile task lists in device memory it allocates itself.
+ * Errors: MMS_EINVAL (offsets decreasing, buffers, workspace), MMS_ENOMEM
+ * (task lists), MMS_EHIP (capture or launch).
+ */
+size_t mms_segmented_workspace_bytes(const uint64_t* h_offsets, uint64_t num_segs, uint32_t flags);
+int mms_segmented_sort(const uint32_t* d_kin, uint32_t* d_kout, const uint32_t* d_vin, uint32_t* d_vout,
+                       const uint64_t* h_offsets, uint64_t num_segs, void* d_ws, size_t ws_bytes,
+                       uint32_t flags, void* stream);
+
+/*
+ * Tuning table (written by the autotuner; §6.2 tunes K and the number of
+ * workers per platform).  A sort whose largest array has n elements uses the
+ * first entry with ceil(log2 n) <= max_log2_n, else the last entry.  fanout
+ * is the merge fan-out K (power of two, 2..16), merge_tile the keys-only
+ * merge output tile (multiple of 256, 1024..8192), variant the merge kernel
+ * shape (0: 64x16-key blocks, 8 waves; 1: 64x8-key blocks, 16 waves;
+ * 2: 64x8-key blocks, 8 waves).  count == 0 restores the built-in default
+ * (K = 16, 8192, variant 0, overridable by MMS_FANOUT / MMS_TOUT /
+ * MMS_MERGE_VARIANT).  Workspace sizes depend on the table: query
+ * mms_workspace_bytes after changing it.  Process-wide, thread-safe.
+ */
+typedef struct {
+    uint32_t max_log2_n;
+    uint32_t fanout;
+    uint32_t merge_tile;
+    uint32_t variant;
+} mms_tuning_t;
+
+int mms_set_tuning(const mms_tuning_t* entries, uint32_t count);
+int mms_get_tuning(uint64_t n, uint32_t flags, mms_tuning_t* out);
+
+/*
  * Per-kernel timing, for measurement harnesses.  While enabled, every kernel
  * the library launches is bracketed by two hipEvents recorded on the stream
  * it is launched on, and mms_timing_read() waits for those events and
@@ -135,7 +182,8 @@ typedef enum {
     MMS_KERNEL_PARTITION = 1,  /* split indices (§4.1)      */
     MMS_KERNEL_MERGE = 2,      /* K-way merge (§4.2)        */
     MMS_KERNEL_COPY = 3,       /* bandwidth probe           */
-    MMS_KERNEL_KINDS = 4
+    MMS_KERNEL_SEGMENTED = 4,  /* one batched graph launch  */
+    MMS_KERNEL_KINDS = 5
 } mms_kernel_kind;
 
 typedef struct {

@@ -11,7 +11,8 @@ from . import _lib
 from ._lib import MMS_KEY_I32, MMS_PAIRS, MmsError, MmsPlan  # noqa: F401
 
 __all__ = ["sort", "sort_pairs", "partition", "copy", "plan", "workspace_bytes", "MmsError",
-           "timing_enable", "timing_reset", "timing_read"]
+           "timing_enable", "timing_reset", "timing_read", "segmented_sort", "segmented_workspace_bytes",
+           "set_tuning", "get_tuning"]
 
 
 def _torch():
@@ -142,3 +143,63 @@ def timing_read() -> dict:
     t = _lib.MmsTiming()
     _lib.check(_lib.lib().mms_timing_read(t))
     return {k: (int(t.launches[i]), float(t.total_ms[i])) for i, k in enumerate(_lib.KERNEL_KINDS)}
+
+
+def segmented_workspace_bytes(offsets, pairs: bool = False) -> int:
+    import numpy as np
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    return int(_lib.lib().mms_segmented_workspace_bytes(off.ctypes.data, off.size - 1,
+                                                        MMS_PAIRS if pairs else 0))
+
+
+def segmented_sort(keys, offsets, values=None, out_keys=None, out_values=None, i32: bool | None = None,
+                   workspace=None, stream=None):
+    """Sort every segment [offsets[s], offsets[s+1]) of a device tensor on its own.
+
+    ``offsets`` is a host sequence of num_segs+1 non-decreasing element
+    offsets.  With ``values`` the sort is stable by key.  Returns ``out_keys``
+    (and ``out_values``).  The batch runs as one hipGraph launch per call once
+    the offsets and buffers repeat.
+    """
+    import numpy as np
+    torch = _torch()
+    _check_u32(keys, "keys")
+    if i32 is None:
+        i32 = keys.dtype == torch.int32
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    if off.ndim != 1 or off.size < 1:
+        raise ValueError("offsets must hold num_segs + 1 entries")
+    if int(off[-1]) > keys.numel():
+        raise ValueError("offsets exceed the keys tensor")
+    pairs = values is not None
+    if out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if pairs:
+        _check_u32(values, "values")
+        if out_values is None:
+            out_values = torch.empty_like(values)
+    need = segmented_workspace_bytes(off, pairs)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=keys.device)
+    elif workspace.numel() * workspace.element_size() < need:
+        raise ValueError(f"workspace needs {need} bytes")
+    _lib.check(_lib.lib().mms_segmented_sort(
+        keys.data_ptr(), out_keys.data_ptr(), values.data_ptr() if pairs else None,
+        out_values.data_ptr() if pairs else None, off.ctypes.data, off.size - 1,
+        workspace.data_ptr(), need, MMS_KEY_I32 if i32 else 0, _stream_ptr(stream)))
+    return (out_keys, out_values) if pairs else out_keys
+
+
+def set_tuning(entries):
+    """Install a tuning table: iterable of (max_log2_n, fanout, merge_tile, variant)."""
+    entries = list(entries)
+    arr = (_lib.MmsTuning * max(1, len(entries)))()
+    for i, (l2, k, t, v) in enumerate(entries):
+        arr[i] = _lib.MmsTuning(int(l2), int(k), int(t), int(v))
+    _lib.check(_lib.lib().mms_set_tuning(arr, len(entries)))
+
+
+def get_tuning(n: int, pairs: bool = False):
+    t = _lib.MmsTuning()
+    _lib.check(_lib.lib().mms_get_tuning(int(n), MMS_PAIRS if pairs else 0, t))
+    return (t.max_log2_n, t.fanout, t.merge_tile, t.variant)

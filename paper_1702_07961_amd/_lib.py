@@ -27,10 +27,11 @@ MMS_KEY_I32 = 0x2
 EXPORTS = [
     "mms_last_error", "mms_version", "mms_plan", "mms_workspace_bytes", "mms_sort_u32",
     "mms_sort_pairs_u32", "mms_partition_u32", "mms_copy_u32", "mms_timing_enable",
-    "mms_timing_reset", "mms_timing_read",
+    "mms_timing_reset", "mms_timing_read", "mms_segmented_workspace_bytes", "mms_segmented_sort",
+    "mms_set_tuning", "mms_get_tuning",
 ]
 
-KERNEL_KINDS = ["tile_sort", "partition", "merge", "copy"]
+KERNEL_KINDS = ["tile_sort", "partition", "merge", "copy", "segmented"]
 
 _vp = ctypes.c_void_p
 _u64 = ctypes.c_uint64
@@ -53,8 +54,17 @@ class MmsPlan(ctypes.Structure):
 
 class MmsTiming(ctypes.Structure):
     _fields_ = [
-        ("launches", ctypes.c_uint64 * 4),
-        ("total_ms", ctypes.c_double * 4),
+        ("launches", ctypes.c_uint64 * 5),
+        ("total_ms", ctypes.c_double * 5),
+    ]
+
+
+class MmsTuning(ctypes.Structure):
+    _fields_ = [
+        ("max_log2_n", ctypes.c_uint32),
+        ("fanout", ctypes.c_uint32),
+        ("merge_tile", ctypes.c_uint32),
+        ("variant", ctypes.c_uint32),
     ]
 
 
@@ -89,6 +99,14 @@ def _declare(lib):
     lib.mms_timing_reset.restype = ctypes.c_int
     lib.mms_timing_read.argtypes = [ctypes.POINTER(MmsTiming)]
     lib.mms_timing_read.restype = ctypes.c_int
+    lib.mms_segmented_workspace_bytes.argtypes = [_vp, _u64, _u32]
+    lib.mms_segmented_workspace_bytes.restype = ctypes.c_size_t
+    lib.mms_segmented_sort.argtypes = [_vp, _vp, _vp, _vp, _vp, _u64, _vp, ctypes.c_size_t, _u32, _vp]
+    lib.mms_segmented_sort.restype = ctypes.c_int
+    lib.mms_set_tuning.argtypes = [ctypes.POINTER(MmsTuning), _u32]
+    lib.mms_set_tuning.restype = ctypes.c_int
+    lib.mms_get_tuning.argtypes = [_u64, _u32, ctypes.POINTER(MmsTuning)]
+    lib.mms_get_tuning.restype = ctypes.c_int
     return lib
 
 

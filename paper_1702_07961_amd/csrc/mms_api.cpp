@@ -1,12 +1,17 @@
-// Host runtime of libmms: plan, workspace layout, argument checks, the round
-// loop, and the C ABI declared in include/mms.h.  Kernels are launched only
-// through the launchers of mms_kernels.hip.
+// Host runtime of libmms: plans, workspace layout, argument checks, the
+// phase loop (base case, then partition + merge per round), the segmented
+// batch with its hipGraph cache, the tuning table, and the C ABI declared in
+// include/mms.h.  Kernels are launched only through the launchers of
+// mms_kernels.hip and mms_merge_keys.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
-#include <cstdlib>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <list>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -28,9 +33,7 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
-int hip_fail(hipError_t e, const char* what) {
-    return fail(MMS_EHIP, "%s: %s", what, hipGetErrorString(e));
-}
+int hip_fail(hipError_t e, const char* what) { return fail(MMS_EHIP, "%s: %s", what, hipGetErrorString(e)); }
 
 // ---- per-kernel timing (mms_timing_*) --------------------------------------
 struct TimingRec {
@@ -43,6 +46,7 @@ std::vector<TimingRec> g_recs;
 std::vector<hipEvent_t> g_pool;
 uint64_t g_launch[MMS_KERNEL_KINDS];
 double g_ms[MMS_KERNEL_KINDS];
+thread_local bool g_capturing = false;   // launches are being captured into a graph
 
 hipEvent_t take_event() {
     if (!g_pool.empty()) {
@@ -55,10 +59,12 @@ hipEvent_t take_event() {
     return e;
 }
 
-// Brackets one kernel launch with events on its stream when timing is on.
+// Brackets one kernel launch (or graph launch) with events on its stream
+// when timing is on.
 class Timed {
   public:
     Timed(int kind, hipStream_t s) : kind_(kind), s_(s) {
+        if (g_capturing) return;
         std::lock_guard<std::mutex> g(g_tmu);
         if (!g_timing) return;
         a_ = take_event();
@@ -78,6 +84,57 @@ class Timed {
     hipEvent_t a_ = nullptr, b_ = nullptr;
 };
 
+// ---- tuning ------------------------------------------------------------------
+// Ordered by max_log2_n; a sort of n uses the first entry with
+// ceil(log2 n) <= max_log2_n (the last entry otherwise).
+std::mutex g_tune_mu;
+std::vector<mms_tuning_t> g_tuning;
+
+struct Tune {
+    uint32_t K;
+    uint32_t Tout;
+    int variant;
+};
+
+uint32_t ceil_log2(uint64_t n) {
+    uint32_t l = 0;
+    while ((1ull << l) < n) ++l;
+    return l;
+}
+
+Tune env_default() {
+    Tune t{mms::kMaxFanout, mms::kToutKeys, 0};
+    if (const char* s = getenv("MMS_TOUT")) t.Tout = (uint32_t)atoi(s);
+    if (const char* s = getenv("MMS_MERGE_VARIANT")) t.variant = atoi(s);
+    if (const char* s = getenv("MMS_FANOUT")) t.K = (uint32_t)atoi(s);
+    return t;
+}
+
+bool valid_tune(uint32_t K, uint32_t Tout, int variant) {
+    return K >= 2 && K <= mms::kMaxFanout && (K & (K - 1)) == 0 && Tout >= 1024 && Tout <= mms::kToutKeys &&
+           Tout % 256 == 0 && variant >= 0 && variant <= 2;
+}
+
+Tune tune_for(uint64_t n, bool pairs) {
+    Tune t = env_default();
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        if (!g_tuning.empty()) {
+            const uint32_t l = ceil_log2(n);
+            const mms_tuning_t* e = &g_tuning.back();
+            for (const auto& x : g_tuning)
+                if (l <= x.max_log2_n) {
+                    e = &x;
+                    break;
+                }
+            t = Tune{e->fanout, e->merge_tile, (int)e->variant};
+        }
+    }
+    if (!valid_tune(t.K, t.Tout, t.variant)) t = Tune{mms::kMaxFanout, mms::kToutKeys, 0};
+    if (pairs) t.Tout = mms::kToutPairs;
+    return t;
+}
+
 // One resident workgroup per compute unit for the persistent merge kernel.
 unsigned persistent_grid() {
     int dev = 0;
@@ -87,36 +144,22 @@ unsigned persistent_grid() {
     return (unsigned)cus;
 }
 
-// Merge kernel shape; MMS_MERGE_VARIANT=1 selects 16 waves with 512-key blocks.
-int merge_variant() {
-    static const int v = [] {
-        const char* s = getenv("MMS_MERGE_VARIANT");
-        return s ? atoi(s) : 0;
-    }();
-    return v;
-}
-
-// Output tile of the keys-only merge; MMS_TOUT overrides (multiple of 256,
-// at most the compiled maximum).
-uint32_t keys_merge_tile() {
-    static const uint32_t v = [] {
-        const char* s = getenv("MMS_TOUT");
-        uint32_t t = s ? (uint32_t)atoi(s) : mms::kToutKeys;
-        if (t < 1024 || t > mms::kToutKeys || t % 256) t = mms::kToutKeys;
-        return t;
-    }();
-    return v;
-}
-
 constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// §6.2: ceil(log_K(ceil(n / T))) merge rounds after the base case.
+uint32_t rounds_for(uint64_t n, uint32_t T, uint32_t K) {
+    uint32_t r = 0;
+    for (uint64_t L = T; L < n; L *= K) ++r;
+    return r;
+}
+
+// ---- plain sort plan ---------------------------------------------------------
 struct Plan {
     uint64_t n;
     bool pairs;
     uint32_t T;
-    uint32_t K;
-    uint32_t Tout;
+    Tune tune;
     uint32_t rounds;
     uint64_t max_tiles;      // largest tile count over the merge rounds
     uint64_t off_vals;       // workspace offsets (bytes)
@@ -124,25 +167,22 @@ struct Plan {
     uint64_t ws_bytes;
 };
 
-// §6.2: ceil(log_K(ceil(n / T))) merge rounds after the base case.
 Plan make_plan(uint64_t n, uint32_t flags) {
     Plan p{};
     p.n = n;
     p.pairs = (flags & MMS_PAIRS) != 0;
     p.T = mms::kT1;
-    p.K = mms::kMaxFanout;
-    p.Tout = p.pairs ? mms::kToutPairs : keys_merge_tile();
-    p.rounds = 0;
+    p.tune = tune_for(n, p.pairs);
+    p.rounds = rounds_for(n, p.T, p.tune.K);
     p.max_tiles = 0;
-    for (uint64_t L = p.T; L < n; L *= p.K) {
-        mms::RoundGeom g = mms::round_geom(n, L, p.K, p.Tout);
-        if (g.tiles > p.max_tiles) p.max_tiles = g.tiles;
-        ++p.rounds;
+    uint64_t L = p.T;
+    for (uint32_t r = 0; r < p.rounds; ++r, L *= p.tune.K) {
+        const mms::RoundGeom g = mms::round_geom(n, L, p.tune.K, p.tune.Tout);
+        p.max_tiles = std::max<uint64_t>(p.max_tiles, g.tiles);
     }
-    const uint64_t kbytes = align_up(n * 4);
-    p.off_vals = kbytes;
+    p.off_vals = align_up(n * 4);
     p.off_table = p.off_vals + (p.pairs ? align_up(n * 4) : 0);
-    p.ws_bytes = p.rounds ? p.off_table + align_up((p.max_tiles + 1) * p.K * 4) : 0;
+    p.ws_bytes = p.rounds ? p.off_table + align_up((p.max_tiles + 1) * p.tune.K * 4) : 0;
     return p;
 }
 
@@ -152,16 +192,11 @@ bool overlaps(const void* a, uint64_t abytes, const void* b, uint64_t bbytes) {
 }
 
 // a and b either coincide exactly or are disjoint
-bool same_or_disjoint(const void* a, const void* b, uint64_t bytes) {
-    return a == b || !overlaps(a, bytes, b, bytes);
-}
+bool same_or_disjoint(const void* a, const void* b, uint64_t bytes) { return a == b || !overlaps(a, bytes, b, bytes); }
 
-int sort_impl(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint64_t n, void* ws,
-              size_t ws_bytes, uint32_t flags, void* stream) {
+int check_buffers(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint64_t n, void* ws,
+                  uint64_t ws_need, size_t ws_bytes) {
     const bool pairs = vin != nullptr;
-    if (flags & ~(MMS_KEY_I32 | MMS_PAIRS)) return fail(MMS_EINVAL, "unknown flags 0x%x", flags);
-    if (n == 0) return MMS_OK;
-    if (n >= (1ull << 32)) return fail(MMS_EINVAL, "n = %llu exceeds 2^32-1", (unsigned long long)n);
     if (!kin || !kout || (pairs && !vout)) return fail(MMS_EINVAL, "null data pointer");
     const uint64_t bytes = n * 4;
     if (!same_or_disjoint(kin, kout, bytes)) return fail(MMS_EINVAL, "keys in/out partially overlap");
@@ -171,54 +206,263 @@ int sort_impl(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t
             overlaps(kout, bytes, vin, bytes) || overlaps(kin, bytes, vout, bytes))
             return fail(MMS_EINVAL, "key and value buffers overlap");
     }
-    const Plan p = make_plan(n, flags | (pairs ? MMS_PAIRS : 0u));
-    if (p.rounds) {
-        if (!ws) return fail(MMS_EINVAL, "workspace required (%llu bytes)", (unsigned long long)p.ws_bytes);
-        if (ws_bytes < p.ws_bytes)
-            return fail(MMS_EINVAL, "workspace too small: %zu < %llu", ws_bytes, (unsigned long long)p.ws_bytes);
+    if (ws_need) {
+        if (!ws) return fail(MMS_EINVAL, "workspace required (%llu bytes)", (unsigned long long)ws_need);
+        if (ws_bytes < ws_need)
+            return fail(MMS_EINVAL, "workspace too small: %zu < %llu", ws_bytes, (unsigned long long)ws_need);
         if ((uintptr_t)ws % kAlign) return fail(MMS_EINVAL, "workspace not 256-byte aligned");
-        if (overlaps(ws, p.ws_bytes, kin, bytes) || overlaps(ws, p.ws_bytes, kout, bytes) ||
-            (pairs && (overlaps(ws, p.ws_bytes, vin, bytes) || overlaps(ws, p.ws_bytes, vout, bytes))))
+        if (overlaps(ws, ws_need, kin, bytes) || overlaps(ws, ws_need, kout, bytes) ||
+            (pairs && (overlaps(ws, ws_need, vin, bytes) || overlaps(ws, ws_need, vout, bytes))))
             return fail(MMS_EINVAL, "workspace overlaps data");
     }
-    hipStream_t s = (hipStream_t)stream;
-    const uint32_t flip = (flags & MMS_KEY_I32) ? 0x80000000u : 0u;
-    uint8_t* wsb = (uint8_t*)ws;
-    uint32_t* ws_k = (uint32_t*)wsb;
-    uint32_t* ws_v = pairs ? (uint32_t*)(wsb + p.off_vals) : nullptr;
-    uint32_t* table = p.rounds ? (uint32_t*)(wsb + p.off_table) : nullptr;
+    return MMS_OK;
+}
 
-    // pass i writes buffer B_i; B_R must be the output, so B_i is the output
-    // when R - i is even and the workspace otherwise
-    auto buf_k = [&](uint32_t i) { return ((p.rounds - i) % 2 == 0) ? kout : ws_k; };
-    auto buf_v = [&](uint32_t i) { return ((p.rounds - i) % 2 == 0) ? vout : ws_v; };
+// ---- the phase loop ----------------------------------------------------------
+struct PhaseList {
+    mms::Phase base;                    // base-case pass
+    std::vector<mms::Phase> rounds;     // merge rounds
+};
 
+int run_phases(bool pairs, const PhaseList& pl, const mms::Bufs& b, uint32_t* table, const Tune& tune,
+               uint32_t flip, hipStream_t s) {
     hipError_t e;
     {
         Timed tm(MMS_KERNEL_TILE_SORT, s);
-        e = mms::launch_tile_sort(pairs, kin, vin, buf_k(0), pairs ? buf_v(0) : nullptr, n, flip,
-                                  p.rounds == 0 ? flip : 0u, s);
+        e = mms::launch_tile_sort(pairs, pl.base, b, flip, s);
     }
     if (e != hipSuccess) return hip_fail(e, "tile sort launch");
-    uint64_t L = p.T;
-    for (uint32_t r = 0; r < p.rounds; ++r, L *= p.K) {
-        const mms::RoundGeom g = mms::round_geom(n, L, p.K, p.Tout);
+    uint64_t L = mms::kT1;
+    for (size_t r = 0; r < pl.rounds.size(); ++r, L *= tune.K) {
+        const mms::Phase& ph = pl.rounds[r];
+        if (ph.tiles == 0) continue;
+        const mms::RoundArgs ra{L, tune.K, tune.Tout, (L * tune.K + tune.Tout - 1) / tune.Tout};
         {
             Timed tm(MMS_KERNEL_PARTITION, s);
-            e = mms::launch_corank_tiles(buf_k(r), g, table, s);
+            e = mms::launch_corank_tiles(ph, b, ra, table, s);
         }
         if (e != hipSuccess) return hip_fail(e, "partition launch");
         {
             Timed tm(MMS_KERNEL_MERGE, s);
-            if (pairs)
-                e = mms::launch_merge(true, buf_k(r), buf_v(r), buf_k(r + 1), buf_v(r + 1), g, table,
-                                      r + 1 == p.rounds ? flip : 0u, s);
-            else
-                e = mms::launch_merge_keys(buf_k(r), buf_k(r + 1), g, table, r + 1 == p.rounds ? flip : 0u,
-                                           persistent_grid(), merge_variant(), s);
+            if (pairs) e = mms::launch_merge_pairs(ph, b, ra, table, flip, s);
+            else e = mms::launch_merge_keys(ph, b, ra, table, flip, persistent_grid(), tune.variant, s);
         }
         if (e != hipSuccess) return hip_fail(e, "merge launch");
     }
+    return MMS_OK;
+}
+
+int sort_impl(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint64_t n, void* ws,
+              size_t ws_bytes, uint32_t flags, void* stream) {
+    const bool pairs = vin != nullptr;
+    if (flags & ~(MMS_KEY_I32 | MMS_PAIRS)) return fail(MMS_EINVAL, "unknown flags 0x%x", flags);
+    if (n == 0) return MMS_OK;
+    if (n >= (1ull << 32)) return fail(MMS_EINVAL, "n = %llu exceeds 2^32-1", (unsigned long long)n);
+    const Plan p = make_plan(n, flags | (pairs ? MMS_PAIRS : 0u));
+    int rc = check_buffers(kin, vin, kout, vout, n, ws, p.ws_bytes, ws_bytes);
+    if (rc) return rc;
+    uint8_t* wsb = (uint8_t*)ws;
+    mms::Bufs b{kin, vin, kout, vout, (uint32_t*)wsb, pairs ? (uint32_t*)(wsb + p.off_vals) : nullptr};
+    uint32_t* table = p.rounds ? (uint32_t*)(wsb + p.off_table) : nullptr;
+    // pass i writes the output when R - i is even, so pass R lands there
+    PhaseList pl;
+    pl.base = mms::Phase{nullptr, n, (p.rounds % 2 == 0) ? 1u : 0u, p.rounds == 0 ? 1u : 0u, (n + p.T - 1) / p.T};
+    uint64_t L = p.T;
+    for (uint32_t r = 0; r < p.rounds; ++r, L *= p.tune.K) {
+        const mms::RoundGeom g = mms::round_geom(n, L, p.tune.K, p.tune.Tout);
+        pl.rounds.push_back(
+            mms::Phase{nullptr, n, ((p.rounds - r - 1) % 2 == 0) ? 1u : 0u, r + 1 == p.rounds ? 1u : 0u, g.tiles});
+    }
+    return run_phases(pairs, pl, b, table, p.tune, (flags & MMS_KEY_I32) ? 0x80000000u : 0u, (hipStream_t)stream);
+}
+
+// ---- segmented batch -----------------------------------------------------------
+// Every segment is sorted as its own plain sort; each phase's tiles of all
+// segments form one task list, so the batch runs one launch per kernel and
+// phase.  Segment s needs R_s rounds; its pass i writes the output when
+// R_s - i is even.
+struct SegPlan {
+    bool pairs;
+    Tune tune;
+    uint64_t total;                              // elements covered (h_offsets[num_segs])
+    std::vector<std::vector<mms::TileTask>> tasks;   // [0] base case, [1 + r] round r
+    uint64_t max_round_tiles;
+    uint64_t off_vals, off_table, ws_bytes;
+};
+
+int make_seg_plan(const uint64_t* off, uint64_t ns, uint32_t flags, SegPlan& sp) {
+    sp.pairs = (flags & MMS_PAIRS) != 0;
+    sp.total = off[ns];
+    uint64_t maxn = 0;
+    for (uint64_t s = 0; s < ns; ++s) {
+        if (off[s + 1] < off[s]) return fail(MMS_EINVAL, "offsets decrease at segment %llu", (unsigned long long)s);
+        maxn = std::max<uint64_t>(maxn, off[s + 1] - off[s]);
+    }
+    if (maxn >= (1ull << 32)) return fail(MMS_EINVAL, "a segment holds 2^32 or more elements");
+    sp.tune = tune_for(maxn ? maxn : 1, sp.pairs);
+    const uint32_t T = mms::kT1, K = sp.tune.K;
+    sp.tasks.assign(1, {});
+    sp.max_round_tiles = 0;
+    for (uint64_t s = 0; s < ns; ++s) {
+        const uint64_t n = off[s + 1] - off[s];
+        if (n == 0) continue;
+        const uint32_t R = rounds_for(n, T, K);
+        if (sp.tasks.size() < (size_t)R + 1) sp.tasks.resize(R + 1);
+        const uint32_t base_info = ((R % 2 == 0) ? mms::kTaskDstOut : 0u) | (R == 0 ? mms::kTaskFinal : 0u);
+        for (uint64_t t = 0; t * T < n; ++t) sp.tasks[0].push_back({off[s], (uint32_t)n, (uint32_t)t | base_info});
+        uint64_t L = T;
+        for (uint32_t r = 0; r < R; ++r, L *= K) {
+            const mms::RoundGeom g = mms::round_geom(n, L, K, sp.tune.Tout);
+            const uint32_t info = (((R - r - 1) % 2 == 0) ? mms::kTaskDstOut : 0u) | (r + 1 == R ? mms::kTaskFinal : 0u);
+            for (uint64_t t = 0; t < g.tiles; ++t) sp.tasks[1 + r].push_back({off[s], (uint32_t)n, (uint32_t)t | info});
+        }
+    }
+    for (size_t r = 1; r < sp.tasks.size(); ++r)
+        sp.max_round_tiles = std::max<uint64_t>(sp.max_round_tiles, sp.tasks[r].size());
+    sp.off_vals = align_up(sp.total * 4);
+    sp.off_table = sp.off_vals + (sp.pairs ? align_up(sp.total * 4) : 0);
+    sp.ws_bytes = sp.off_table + align_up((sp.max_round_tiles + 1) * K * 4);
+    return MMS_OK;
+}
+
+// A captured batch: task lists in device memory owned by the library and the
+// instantiated graph of all launches, keyed by offsets, pointers and tuning.
+struct SegEntry {
+    std::string key;
+    SegPlan plan;
+    mms::TileTask* d_tasks = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+std::mutex g_seg_mu;
+std::list<SegEntry> g_seg_cache;   // most recent first
+constexpr size_t kSegCacheMax = 8;
+
+void drop_entry(SegEntry& e) {
+    if (e.exec) hipGraphExecDestroy(e.exec);
+    if (e.graph) hipGraphDestroy(e.graph);
+    if (e.d_tasks) hipFree(e.d_tasks);
+    e.exec = nullptr;
+    e.graph = nullptr;
+    e.d_tasks = nullptr;
+}
+
+std::string seg_key(const uint64_t* off, uint64_t ns, uint32_t flags, const void* const* ptrs, int nptr,
+                    const Tune& t) {
+    std::string k;
+    auto put = [&](const void* p, size_t n) { k.append((const char*)p, n); };
+    put(&ns, sizeof ns);
+    put(&flags, sizeof flags);
+    put(&t, sizeof t);
+    for (int i = 0; i < nptr; ++i) put(&ptrs[i], sizeof(void*));
+    put(off, (ns + 1) * sizeof(uint64_t));
+    return k;
+}
+
+bool seg_graph_enabled() {
+    static const bool on = [] {
+        const char* s = getenv("MMS_NO_GRAPH");
+        return !(s && atoi(s) != 0);
+    }();
+    return on;
+}
+
+int segmented_impl(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uint32_t* vout, const uint64_t* off,
+                   uint64_t ns, void* ws, size_t ws_bytes, uint32_t flags, hipStream_t s) {
+    const bool pairs = vin != nullptr;
+    if (flags & ~(MMS_KEY_I32 | MMS_PAIRS)) return fail(MMS_EINVAL, "unknown flags 0x%x", flags);
+    if (ns == 0) return MMS_OK;
+    if (!off) return fail(MMS_EINVAL, "null offsets");
+    SegPlan sp;
+    int rc = make_seg_plan(off, ns, flags | (pairs ? MMS_PAIRS : 0u), sp);
+    if (rc) return rc;
+    if (sp.total == 0) return MMS_OK;
+    rc = check_buffers(kin, vin, kout, vout, sp.total, ws, sp.ws_bytes, ws_bytes);
+    if (rc) return rc;
+
+    const void* ptrs[5] = {kin, kout, vin, vout, ws};
+    const std::string key = seg_key(off, ns, flags | (pairs ? MMS_PAIRS : 0u), ptrs, 5, sp.tune);
+    std::lock_guard<std::mutex> lock(g_seg_mu);
+    auto it = std::find_if(g_seg_cache.begin(), g_seg_cache.end(), [&](const SegEntry& e) { return e.key == key; });
+    if (it == g_seg_cache.end()) {
+        SegEntry e;
+        e.key = key;
+        e.plan = std::move(sp);
+        size_t ntasks = 0;
+        for (auto& v : e.plan.tasks) ntasks += v.size();
+        hipError_t he = hipMalloc(&e.d_tasks, std::max<size_t>(ntasks, 1) * sizeof(mms::TileTask));
+        if (he != hipSuccess) return fail(MMS_ENOMEM, "task list allocation: %s", hipGetErrorString(he));
+        size_t at = 0;
+        for (auto& v : e.plan.tasks) {
+            if (!v.empty()) {
+                he = hipMemcpy(e.d_tasks + at, v.data(), v.size() * sizeof(mms::TileTask), hipMemcpyHostToDevice);
+                if (he != hipSuccess) {
+                    drop_entry(e);
+                    return hip_fail(he, "task list upload");
+                }
+            }
+            at += v.size();
+        }
+        g_seg_cache.push_front(std::move(e));
+        while (g_seg_cache.size() > kSegCacheMax) {
+            drop_entry(g_seg_cache.back());
+            g_seg_cache.pop_back();
+        }
+        it = g_seg_cache.begin();
+    } else if (it != g_seg_cache.begin()) {
+        g_seg_cache.splice(g_seg_cache.begin(), g_seg_cache, it);
+        it = g_seg_cache.begin();
+    }
+    SegEntry& e = *it;
+    const SegPlan& p = e.plan;
+    uint8_t* wsb = (uint8_t*)ws;
+    mms::Bufs b{kin, vin, kout, vout, (uint32_t*)wsb, pairs ? (uint32_t*)(wsb + p.off_vals) : nullptr};
+    uint32_t* table = (uint32_t*)(wsb + p.off_table);
+    PhaseList pl;
+    size_t at = 0;
+    for (size_t i = 0; i < p.tasks.size(); ++i) {
+        const mms::Phase ph{e.d_tasks + at, 0, 0, 0, p.tasks[i].size()};
+        if (i == 0) pl.base = ph;
+        else pl.rounds.push_back(ph);
+        at += p.tasks[i].size();
+    }
+    const uint32_t flip = (flags & MMS_KEY_I32) ? 0x80000000u : 0u;
+    if (!seg_graph_enabled()) return run_phases(pairs, pl, b, table, p.tune, flip, s);
+
+    if (!e.exec) {
+        hipStream_t cap = nullptr;
+        hipError_t he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (he != hipSuccess) return hip_fail(he, "capture stream");
+        he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (he != hipSuccess) {
+            hipStreamDestroy(cap);
+            return hip_fail(he, "begin capture");
+        }
+        g_capturing = true;
+        rc = run_phases(pairs, pl, b, table, p.tune, flip, cap);
+        g_capturing = false;
+        hipGraph_t graph = nullptr;
+        he = hipStreamEndCapture(cap, &graph);
+        hipStreamDestroy(cap);
+        if (rc) {
+            if (graph) hipGraphDestroy(graph);
+            return rc;
+        }
+        if (he != hipSuccess) return hip_fail(he, "end capture");
+        he = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+        if (he != hipSuccess) {
+            hipGraphDestroy(graph);
+            return hip_fail(he, "graph instantiate");
+        }
+        e.graph = graph;
+    }
+    hipError_t he;
+    {
+        Timed tm(MMS_KERNEL_SEGMENTED, s);
+        he = hipGraphLaunch(e.exec, s);
+    }
+    if (he != hipSuccess) return hip_fail(he, "graph launch");
     return MMS_OK;
 }
 
@@ -228,7 +472,7 @@ extern "C" {
 
 const char* mms_last_error(void) { return g_err.c_str(); }
 
-int mms_version(void) { return 100; }
+int mms_version(void) { return 200; }
 
 int mms_plan(uint64_t n, uint32_t flags, mms_plan_t* out) {
     if (!out) return fail(MMS_EINVAL, "null plan pointer");
@@ -239,8 +483,8 @@ int mms_plan(uint64_t n, uint32_t flags, mms_plan_t* out) {
     out->flags = flags;
     out->tile = p.T;
     out->lanes_per_tile = mms::kW1 * 64;
-    out->fanout = p.K;
-    out->merge_tile = p.Tout;
+    out->fanout = p.tune.K;
+    out->merge_tile = p.tune.Tout;
     out->rounds = n ? p.rounds : 0;
     out->passes = n ? 1 + p.rounds : 0;
     out->workspace_bytes = p.ws_bytes;
@@ -262,6 +506,44 @@ int mms_sort_pairs_u32(const uint32_t* d_kin, const uint32_t* d_vin, uint32_t* d
                        uint64_t n, void* d_ws, size_t ws_bytes, uint32_t flags, void* stream) {
     if (n && !d_vin) return fail(MMS_EINVAL, "null value pointer");
     return sort_impl(d_kin, d_vin, d_kout, d_vout, n, d_ws, ws_bytes, flags & ~MMS_PAIRS, stream);
+}
+
+size_t mms_segmented_workspace_bytes(const uint64_t* h_offsets, uint64_t num_segs, uint32_t flags) {
+    if (!h_offsets || num_segs == 0) return 0;
+    SegPlan sp;
+    if (make_seg_plan(h_offsets, num_segs, flags, sp)) return 0;
+    return sp.total ? (size_t)sp.ws_bytes : 0;
+}
+
+int mms_segmented_sort(const uint32_t* d_kin, uint32_t* d_kout, const uint32_t* d_vin, uint32_t* d_vout,
+                       const uint64_t* h_offsets, uint64_t num_segs, void* d_ws, size_t ws_bytes, uint32_t flags,
+                       void* stream) {
+    if ((d_vin == nullptr) != (d_vout == nullptr)) return fail(MMS_EINVAL, "values need both input and output");
+    return segmented_impl(d_kin, d_kout, d_vin, d_vout, h_offsets, num_segs, d_ws, ws_bytes, flags & ~MMS_PAIRS,
+                          (hipStream_t)stream);
+}
+
+int mms_set_tuning(const mms_tuning_t* entries, uint32_t count) {
+    if (count && !entries) return fail(MMS_EINVAL, "null tuning table");
+    std::vector<mms_tuning_t> v(entries, entries + count);
+    for (const auto& x : v)
+        if (!valid_tune(x.fanout, x.merge_tile, (int)x.variant))
+            return fail(MMS_EINVAL, "invalid tuning entry (fanout %u, merge_tile %u, variant %u)", x.fanout,
+                        x.merge_tile, x.variant);
+    std::sort(v.begin(), v.end(), [](const mms_tuning_t& a, const mms_tuning_t& b) { return a.max_log2_n < b.max_log2_n; });
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tuning = std::move(v);
+    return MMS_OK;
+}
+
+int mms_get_tuning(uint64_t n, uint32_t flags, mms_tuning_t* out) {
+    if (!out) return fail(MMS_EINVAL, "null tuning pointer");
+    const Tune t = tune_for(n ? n : 1, (flags & MMS_PAIRS) != 0);
+    out->max_log2_n = ceil_log2(n ? n : 1);
+    out->fanout = t.K;
+    out->merge_tile = t.Tout;
+    out->variant = (uint32_t)t.variant;
+    return MMS_OK;
 }
 
 int mms_partition_u32(const uint32_t* d_keys, uint64_t n, uint64_t run_len, uint32_t K, const uint64_t* d_group,

@@ -2,8 +2,13 @@
 //
 //   tile_sort   base case (§4.3): sort tiles of T1 elements on chip
 //   corank      partition (§4.1): split indices of K sorted runs at a rank
-//   merge       K-way merge of one output tile through LDS (§4.2, §7)
+//   merge       K-way merge of one output tile through LDS (§4.2, §7),
+//               key-value path (the keys-only path is mms_merge_keys.hip)
 //   copy        streaming copy, the bandwidth probe
+//
+// Every sorting kernel works on a Phase: a list of tiles, each inside one
+// segment (the plain sort is one segment).  Positions are segment-relative;
+// a tile's task says whether its pass writes the output or the workspace.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -21,10 +26,7 @@ namespace mms {
 // are never stored.
 // ===========================================================================
 template <int E, int W, bool P>
-__global__ __launch_bounds__(W * 64) void k_tile_sort(const uint32_t* __restrict__ in_k,
-                                                      const uint32_t* __restrict__ in_v, uint32_t* out_k,
-                                                      uint32_t* out_v, uint64_t n, uint32_t flip_in,
-                                                      uint32_t flip_out) {
+__global__ __launch_bounds__(W * 64) void k_tile_sort(Phase ph, Bufs b, uint32_t flip) {
     constexpr uint32_t CH = 64u * E;
     constexpr uint32_t T = CH * W;
     extern __shared__ __align__(16) uint32_t smem[];
@@ -37,16 +39,22 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort(const uint32_t* __restrict
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const uint64_t base = (uint64_t)blockIdx.x * T;
-    const uint32_t cnt = (uint32_t)min<uint64_t>(T, n - base);
+    const TileRef tr = tile_ref(ph, blockIdx.x);
+    const uint64_t base = tr.base + (uint64_t)tr.local * T;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(T, tr.n - (uint64_t)tr.local * T);
+    const uint32_t* in_k = b.in_k + base;
+    const uint32_t* in_v = P ? b.in_v + base : nullptr;
+    uint32_t* out_k = (tr.dst_out ? b.out_k : b.ws_k) + base;
+    uint32_t* out_v = P ? (tr.dst_out ? b.out_v : b.ws_v) + base : nullptr;
+    const uint32_t flip_out = tr.final_pass ? flip : 0u;
 
     Elem<P> r[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t j = (uint32_t)wave * CH + (uint32_t)e * 64u + (uint32_t)lane;
         if (j < cnt) {
-            if constexpr (P) r[e] = Elem<P>{in_k[base + j] ^ flip_in, j, in_v[base + j]};
-            else r[e] = Elem<P>{in_k[base + j] ^ flip_in};
+            if constexpr (P) r[e] = Elem<P>{in_k[j] ^ flip, j, in_v[j]};
+            else r[e] = Elem<P>{in_k[j] ^ flip};
         } else {
             r[e] = Elem<P>::sentinel();
         }
@@ -62,12 +70,12 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort(const uint32_t* __restrict
     __syncthreads();
 
     uint32_t* wscr = scr + (uint32_t)wave * Xpose<kEM1>::WORDS;
-    const bool vec = ((uintptr_t)(out_k + base) & 15u) == 0;
+    const bool vec = ((uintptr_t)out_k & 15u) == 0;
     for (uint32_t lvl = 0; (1u << lvl) < (uint32_t)W; ++lvl) {
         const bool last = (2u << lvl) >= (uint32_t)W;
         if constexpr (P) {
             if (last) {
-                GlobalSinkLim<P> out{out_k + base, out_v + base, flip_out, cnt};
+                GlobalSinkLim<P> out{out_k, out_v, flip_out, cnt};
                 merge_level<kEM, P>(Xk, Xv, seg0, W, lvl, T, out, wave, W, lane);
             } else {
                 LdsSink<P> out{Yk, Yv};
@@ -75,7 +83,7 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort(const uint32_t* __restrict
             }
         } else {
             if (last) {
-                GlobalSinkKeys out{out_k + base, flip_out, cnt, vec};
+                GlobalSinkKeys out{out_k, flip_out, cnt, vec};
                 merge_level_keys<kEM1>(Xk, seg0, seg0, W, lvl, out, wscr, wave, W, lane);
             } else {
                 LdsSinkKeys out{Yk};
@@ -178,20 +186,22 @@ __device__ uint64_t corank_wave(const uint32_t* __restrict__ keys, uint64_t gb, 
 }
 
 // One wave per tile of a merge round: the split at the tile's first output.
-__global__ __launch_bounds__(256) void k_corank_tiles(const uint32_t* __restrict__ src, uint64_t n, uint64_t L,
-                                                      uint32_t K, uint32_t Tout, uint64_t tpg, uint64_t tiles,
-                                                      uint32_t* __restrict__ table) {
+// The round reads the buffer its tasks do not write.
+__global__ __launch_bounds__(256) void k_corank_tiles(Phase ph, Bufs b, RoundArgs ra, uint32_t* __restrict__ table) {
     const int lane = threadIdx.x & 63;
     const uint64_t t = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (t >= tiles) return;
-    const uint64_t g = t / tpg;
-    const uint64_t i = t - g * tpg;
-    const uint64_t gb = g * (uint64_t)K * L;
-    const uint64_t glen = min((uint64_t)K * L, n - gb);
-    const uint32_t Kg = (uint32_t)((glen + L - 1) / L);
+    if (t >= ph.tiles) return;
+    const TileRef tr = tile_ref(ph, t);
+    const uint32_t* src = tr.dst_out ? b.ws_k : b.out_k;
+    const uint32_t grp = tr.local / (uint32_t)ra.tpg;
+    const uint64_t i = tr.local - (uint64_t)grp * ra.tpg;
+    const uint64_t span = (uint64_t)ra.K * ra.L;
+    const uint64_t gb = (uint64_t)grp * span;
+    const uint64_t glen = min(span, tr.n - gb);
+    const uint32_t Kg = (uint32_t)((glen + ra.L - 1) / ra.L);
     uint64_t c = 0;
-    if (i > 0) c = corank_wave(src, gb, glen, L, Kg, i * (uint64_t)Tout, 0u, lane);
-    if ((uint32_t)lane < K) table[t * K + (uint64_t)lane] = (uint32_t)c;
+    if (i > 0) c = corank_wave(src, tr.base + gb, glen, ra.L, Kg, i * (uint64_t)ra.Tout, 0u, lane);
+    if ((uint32_t)lane < ra.K) table[t * ra.K + (uint64_t)lane] = (uint32_t)c;
 }
 
 __global__ __launch_bounds__(256) void k_corank_queries(const uint32_t* __restrict__ keys, uint64_t n,
@@ -218,33 +228,40 @@ __global__ __launch_bounds__(256) void k_corank_queries(const uint32_t* __restri
 }
 
 // ===========================================================================
-// Merge (§4.2, §7): one workgroup per output tile of a round.  The tile's
-// pieces of its group's K runs, bounded by the split indices of its first
-// and last output, are loaded into LDS back to back, merged pairwise level
-// by level inside LDS (log2 K levels), and the last level is written to
+// Key-value merge (§4.2, §7): one workgroup per output tile of a round.  The
+// tile's pieces of its group's K runs, bounded by the split indices of its
+// first and last output, are loaded into LDS back to back, merged pairwise
+// level by level inside LDS (log2 K levels), and the last level is written to
 // memory.  A group holding a single run is copied.
 // ===========================================================================
-template <int W, bool P>
-__global__ __launch_bounds__(W * 64) void k_merge(const uint32_t* __restrict__ src_k,
-                                                  const uint32_t* __restrict__ src_v, uint32_t* dst_k,
-                                                  uint32_t* dst_v, uint64_t n, uint64_t L, uint32_t K,
-                                                  uint32_t Tout, uint64_t tpg,
-                                                  const uint32_t* __restrict__ table, uint32_t flip_out) {
+template <int W>
+__global__ __launch_bounds__(W * 64) void k_merge_pairs(Phase ph, Bufs b, RoundArgs ra,
+                                                        const uint32_t* __restrict__ table, uint32_t flip) {
+    constexpr bool P = true;
+    const uint32_t Tout = ra.Tout, K = ra.K;
+    const uint64_t L = ra.L;
     extern __shared__ uint32_t smem[];
     uint32_t* Xk = smem;
     uint32_t* Yk = smem + Tout;
-    uint32_t* Xv = P ? smem + 2 * Tout : nullptr;
-    uint32_t* Yv = P ? smem + 3 * Tout : nullptr;
-    uint32_t* seg0 = smem + (P ? 4 : 2) * Tout;   // [kMaxFanout + 1]
+    uint32_t* Xv = smem + 2 * Tout;
+    uint32_t* Yv = smem + 3 * Tout;
+    uint32_t* seg0 = smem + 4 * Tout;             // [kMaxFanout + 1]
     uint32_t* start = seg0 + kMaxFanout + 1;      // [kMaxFanout]
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const uint64_t t = blockIdx.x;
-    const uint64_t g = t / tpg;
-    const uint64_t i = t - g * tpg;
-    const uint64_t gb = g * (uint64_t)K * L;
-    const uint64_t glen = min((uint64_t)K * L, n - gb);
+    const TileRef tr = tile_ref(ph, t);
+    const uint32_t* src_k = (tr.dst_out ? b.ws_k : b.out_k) + tr.base;
+    const uint32_t* src_v = (tr.dst_out ? b.ws_v : b.out_v) + tr.base;
+    uint32_t* dst_k = (tr.dst_out ? b.out_k : b.ws_k) + tr.base;
+    uint32_t* dst_v = (tr.dst_out ? b.out_v : b.ws_v) + tr.base;
+    const uint32_t flip_out = tr.final_pass ? flip : 0u;
+    const uint32_t grp = tr.local / (uint32_t)ra.tpg;
+    const uint64_t i = tr.local - (uint64_t)grp * ra.tpg;
+    const uint64_t span = (uint64_t)K * L;
+    const uint64_t gb = (uint64_t)grp * span;
+    const uint64_t glen = min(span, tr.n - gb);
     const uint32_t Kg = (uint32_t)((glen + L - 1) / L);
     const uint64_t obeg = i * (uint64_t)Tout;
     const uint32_t cnt = (uint32_t)min<uint64_t>(Tout, glen - obeg);
@@ -253,7 +270,7 @@ __global__ __launch_bounds__(W * 64) void k_merge(const uint32_t* __restrict__ s
     if (Kg == 1) {   // a lone run: its tile is already in order
         for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
             dst_k[obase + j] = src_k[obase + j] ^ flip_out;
-            if constexpr (P) dst_v[obase + j] = src_v[obase + j];
+            dst_v[obase + j] = src_v[obase + j];
         }
         return;
     }
@@ -277,7 +294,7 @@ __global__ __launch_bounds__(W * 64) void k_merge(const uint32_t* __restrict__ s
         const uint64_t src0 = gb + (uint64_t)k * L + start[k];
         for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) {
             Xk[dst0 + j] = src_k[src0 + j];
-            if constexpr (P) Xv[dst0 + j] = src_v[src0 + j];
+            Xv[dst0 + j] = src_v[src0 + j];
         }
     }
     __syncthreads();
@@ -285,7 +302,7 @@ __global__ __launch_bounds__(W * 64) void k_merge(const uint32_t* __restrict__ s
     for (uint32_t lvl = 0; (1u << lvl) < Kg; ++lvl) {
         const bool last = (2u << lvl) >= Kg;
         if (last) {
-            GlobalSinkLim<P> out{dst_k + obase, P ? dst_v + obase : nullptr, flip_out, cnt};
+            GlobalSinkLim<P> out{dst_k + obase, dst_v + obase, flip_out, cnt};
             merge_level<kEM, P>(Xk, Xv, seg0, Kg, lvl, cnt, out, wave, W, lane);
         } else {
             LdsSink<P> out{Yk, Yv};
@@ -321,8 +338,9 @@ RoundGeom round_geom(uint64_t n, uint64_t L, uint32_t K, uint32_t Tout) {
     g.K = K;
     g.Tout = Tout;
     const uint64_t span = (uint64_t)K * L;
-    g.groups = (n + span - 1) / span;
     g.tiles_per_group = (span + Tout - 1) / Tout;
+    if (n == 0) return g;
+    g.groups = (n + span - 1) / span;
     const uint64_t last = n - (g.groups - 1) * span;
     g.tiles = (g.groups - 1) * g.tiles_per_group + (last + Tout - 1) / Tout;
     return g;
@@ -332,29 +350,28 @@ static hipError_t allow_lds(const void* f, size_t bytes) {
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-hipError_t launch_tile_sort(bool pairs, const uint32_t* in_k, const uint32_t* in_v, uint32_t* out_k,
-                            uint32_t* out_v, uint64_t n, uint32_t flip_in, uint32_t flip_out, hipStream_t s) {
-    const uint64_t blocks = (n + kT1 - 1) / kT1;
+hipError_t launch_tile_sort(bool pairs, const Phase& ph, const Bufs& b, uint32_t flip, hipStream_t s) {
+    if (ph.tiles == 0) return hipSuccess;
     if (pairs) {
         const size_t lds = (4u * kT1 + 32u) * sizeof(uint32_t);
         hipError_t e = allow_lds((const void*)k_tile_sort<kE1, kW1, true>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_tile_sort<kE1, kW1, true>), dim3((unsigned)blocks), dim3(kW1 * 64), lds, s, in_k, in_v,
-                           out_k, out_v, n, flip_in, flip_out);
+        hipLaunchKernelGGL((k_tile_sort<kE1, kW1, true>), dim3((unsigned)ph.tiles), dim3(kW1 * 64), lds, s, ph, b,
+                           flip);
     } else {
         const size_t lds = (2u * kT1 + 32u + kW1 * Xpose<kEM1>::WORDS) * sizeof(uint32_t);
         hipError_t e = allow_lds((const void*)k_tile_sort<kE1, kW1, false>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_tile_sort<kE1, kW1, false>), dim3((unsigned)blocks), dim3(kW1 * 64), lds, s, in_k,
-                           in_v, out_k, out_v, n, flip_in, flip_out);
+        hipLaunchKernelGGL((k_tile_sort<kE1, kW1, false>), dim3((unsigned)ph.tiles), dim3(kW1 * 64), lds, s, ph, b,
+                           flip);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_corank_tiles(const uint32_t* src, const RoundGeom& g, uint32_t* table, hipStream_t s) {
-    const uint64_t blocks = (g.tiles + 3) / 4;
-    hipLaunchKernelGGL(k_corank_tiles, dim3((unsigned)blocks), dim3(256), 0, s, src, g.n, g.L, g.K, g.Tout,
-                       g.tiles_per_group, g.tiles, table);
+hipError_t launch_corank_tiles(const Phase& ph, const Bufs& b, const RoundArgs& ra, uint32_t* table, hipStream_t s) {
+    if (ph.tiles == 0) return hipSuccess;
+    const uint64_t blocks = (ph.tiles + 3) / 4;
+    hipLaunchKernelGGL(k_corank_tiles, dim3((unsigned)blocks), dim3(256), 0, s, ph, b, ra, table);
     return hipGetLastError();
 }
 
@@ -366,22 +383,13 @@ hipError_t launch_corank_queries(const uint32_t* keys, uint64_t n, uint64_t L, u
     return hipGetLastError();
 }
 
-size_t merge_lds_bytes(bool pairs, uint32_t Tout, uint32_t K) {
-    if (pairs) return ((4u * Tout + 2u * kMaxFanout + 8u) * sizeof(uint32_t));
-    return (2u * (Tout + 4u * K) + kW3 * Xpose<kEM3>::WORDS + 3u * (kMaxFanout + 1u)) * sizeof(uint32_t);
-}
-
-hipError_t launch_merge(bool pairs, const uint32_t* src_k, const uint32_t* src_v, uint32_t* dst_k, uint32_t* dst_v,
-                        const RoundGeom& g, const uint32_t* table, uint32_t flip_out, hipStream_t s) {
-    const size_t lds = merge_lds_bytes(pairs, g.Tout, g.K);
-    if (pairs) {
-        hipError_t e = allow_lds((const void*)k_merge<kW3, true>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_merge<kW3, true>), dim3((unsigned)g.tiles), dim3(kW3 * 64), lds, s, src_k, src_v, dst_k,
-                           dst_v, g.n, g.L, g.K, g.Tout, g.tiles_per_group, table, flip_out);
-    } else {
-        return hipErrorInvalidValue;   // keys use launch_merge_keys
-    }
+hipError_t launch_merge_pairs(const Phase& ph, const Bufs& b, const RoundArgs& ra, const uint32_t* table,
+                              uint32_t flip, hipStream_t s) {
+    if (ph.tiles == 0) return hipSuccess;
+    const size_t lds = (4u * ra.Tout + 2u * kMaxFanout + 8u) * sizeof(uint32_t);
+    hipError_t e = allow_lds((const void*)k_merge_pairs<kW3>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_merge_pairs<kW3>), dim3((unsigned)ph.tiles), dim3(kW3 * 64), lds, s, ph, b, ra, table, flip);
     return hipGetLastError();
 }
 

@@ -22,28 +22,34 @@ namespace mms {
 namespace {
 
 struct TileGeo {
-    uint64_t gb;      // group start
+    uint64_t gb;      // group start (absolute position)
     uint64_t glen;    // group size
     uint64_t obeg;    // tile start inside the group
     uint32_t Kg;      // runs in the group
     uint32_t cnt;     // outputs of the tile
     bool first;       // first tile of its group
     bool last;        // last tile of its group
+    bool dst_out;     // the pass writes the output buffer
+    bool final_pass;  // last pass of the segment
 };
 
-__device__ __forceinline__ TileGeo tile_geo(uint64_t t, uint64_t n, uint64_t L, uint32_t K, uint32_t Tout,
-                                            uint64_t tpg) {
+__device__ __forceinline__ TileGeo tile_geo(const Phase& ph, uint64_t t, const RoundArgs& ra) {
+    const TileRef tr = tile_ref(ph, t);
     TileGeo g;
     // tile counts stay far below 2^32, so 32-bit division suffices
-    const uint32_t grp = (uint32_t)t / (uint32_t)tpg;
-    const uint64_t i = t - (uint64_t)grp * tpg;
-    g.gb = grp * (uint64_t)K * L;
-    g.glen = min((uint64_t)K * L, n - g.gb);
-    g.Kg = (uint32_t)((g.glen + L - 1) / L);
-    g.obeg = i * (uint64_t)Tout;
-    g.cnt = (uint32_t)min<uint64_t>(Tout, g.glen - g.obeg);
+    const uint32_t grp = tr.local / (uint32_t)ra.tpg;
+    const uint64_t i = tr.local - (uint64_t)grp * ra.tpg;
+    const uint64_t span = (uint64_t)ra.K * ra.L;
+    const uint64_t gb = (uint64_t)grp * span;
+    g.gb = tr.base + gb;
+    g.glen = min(span, tr.n - gb);
+    g.Kg = (uint32_t)((g.glen + ra.L - 1) / ra.L);
+    g.obeg = i * (uint64_t)ra.Tout;
+    g.cnt = (uint32_t)min<uint64_t>(ra.Tout, g.glen - g.obeg);
     g.first = i == 0;
-    g.last = g.obeg + Tout >= g.glen;
+    g.last = g.obeg + ra.Tout >= g.glen;
+    g.dst_out = tr.dst_out;
+    g.final_pass = tr.final_pass;
     return g;
 }
 
@@ -117,11 +123,12 @@ __device__ __forceinline__ void build_meta(const Meta& m, uint32_t s, uint32_t e
 }  // namespace
 
 template <int EM, int W, int PF>
-__global__ __launch_bounds__(W * 64) void k_merge_keys(const uint32_t* __restrict__ src, uint32_t* dst, uint64_t n,
-                                                       uint64_t L, uint32_t K, uint32_t Tout, uint64_t tpg,
-                                                       uint64_t tiles, const uint32_t* __restrict__ table,
-                                                       uint32_t flip_out) {
+__global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundArgs ra,
+                                                       const uint32_t* __restrict__ table, uint32_t flip) {
     constexpr uint32_t NT = W * 64;
+    const uint64_t L = ra.L;
+    const uint32_t K = ra.K, Tout = ra.Tout;
+    const uint64_t tiles = ph.tiles;
     extern __shared__ __align__(16) uint32_t smem[];
     const uint32_t cap = Tout + 4u * K;
     uint32_t* bufA = smem;
@@ -129,8 +136,8 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(const uint32_t* __restric
     uint32_t* scr = smem + 2 * cap;
     uint32_t* mbase = scr + W * Xpose<EM>::WORDS;     // two piece tables of kMetaWords
     auto meta = [&](int which) {
-        uint32_t* b = mbase + kMetaWords * (uint32_t)which;
-        return Meta{b, b + 17, b + 34, b + 51};
+        uint32_t* mb = mbase + kMetaWords * (uint32_t)which;
+        return Meta{mb, mb + 17, mb + 34, mb + 51};
     };
 
     const int lane = threadIdx.x & 63;
@@ -138,7 +145,7 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(const uint32_t* __restric
     const uint32_t tid = threadIdx.x;
     const uint64_t G = gridDim.x;
     uint32_t* wscr = scr + (uint32_t)wave * Xpose<EM>::WORDS;
-    const bool vec_base = ((uintptr_t)dst & 15u) == 0;
+    const bool vec_base = (((uintptr_t)b.out_k | (uintptr_t)b.ws_k) & 15u) == 0;
 
     uint64_t t = blockIdx.x;
     if (t >= tiles) return;
@@ -149,7 +156,8 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(const uint32_t* __restric
     uint32_t nx_s = 0, nx_e = 0;   // wave 0: split indices of the tile after next
 
     auto issue_loads = [&](uint64_t tt, const Meta& m) {
-        const TileGeo g = tile_geo(tt, n, L, K, Tout, tpg);
+        const TileGeo g = tile_geo(ph, tt, ra);
+        const uint32_t* src = g.dst_out ? b.ws_k : b.out_k;
 #pragma unroll
         for (int r = 0; r < PF; ++r) {
             const uint32_t j = (uint32_t)r * NT + tid;
@@ -171,12 +179,12 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(const uint32_t* __restric
 
     // prologue: piece table and keys of the first tile, split of the second
     {
-        const TileGeo g0 = tile_geo(t, n, L, K, Tout, tpg);
+        const TileGeo g0 = tile_geo(ph, t, ra);
         if (wave == 0) {
             uint32_t s, e;
             load_split(table, t, g0, L, K, lane, s, e);
             build_meta(meta(0), s, e, g0, lane);
-            if (t + G < tiles) load_split(table, t + G, tile_geo(t + G, n, L, K, Tout, tpg), L, K, lane, nx_s, nx_e);
+            if (t + G < tiles) load_split(table, t + G, tile_geo(ph, t + G, ra), L, K, lane, nx_s, nx_e);
         }
         __syncthreads();
         issue_loads(t, meta(0));
@@ -186,7 +194,9 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(const uint32_t* __restric
 
     int cur = 0;
     for (;;) {
-        const TileGeo g = tile_geo(t, n, L, K, Tout, tpg);
+        const TileGeo g = tile_geo(ph, t, ra);
+        uint32_t* dst = g.dst_out ? b.out_k : b.ws_k;
+        const uint32_t flip_out = g.final_pass ? flip : 0u;
         const Meta mc = meta(cur);
         const Meta mn = meta(cur ^ 1);
         const uint64_t tn = t + G;
@@ -194,10 +204,10 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(const uint32_t* __restric
 
         // wave 0: piece table of the next tile, split indices of the one after
         if (wave == 0 && has_next) {
-            const TileGeo gn = tile_geo(tn, n, L, K, Tout, tpg);
+            const TileGeo gn = tile_geo(ph, tn, ra);
             build_meta(mn, nx_s, nx_e, gn, lane);
             if (tn + G < tiles)
-                load_split(table, tn + G, tile_geo(tn + G, n, L, K, Tout, tpg), L, K, lane, nx_s, nx_e);
+                load_split(table, tn + G, tile_geo(ph, tn + G, ra), L, K, lane, nx_s, nx_e);
         }
 
         uint32_t* X = bufA;
@@ -246,10 +256,10 @@ static hipError_t allow_lds(const void* f, size_t bytes) {
 }
 
 template <int EM, int W>
-static hipError_t launch_variant(const uint32_t* src, uint32_t* dst, const RoundGeom& g, const uint32_t* table,
-                                 uint32_t flip_out, unsigned grid, hipStream_t s) {
+static hipError_t launch_variant(const Phase& ph, const Bufs& b, const RoundArgs& ra, const uint32_t* table,
+                                 uint32_t flip, unsigned grid, hipStream_t s) {
     constexpr int PF = (int)((kToutKeys + W * 64 - 1) / (W * 64));
-    const size_t lds = (2u * (g.Tout + 4u * g.K) + W * Xpose<EM>::WORDS + 2u * kMetaWords) * sizeof(uint32_t);
+    const size_t lds = (2u * (ra.Tout + 4u * ra.K) + W * Xpose<EM>::WORDS + 2u * kMetaWords) * sizeof(uint32_t);
     hipError_t e = allow_lds((const void*)k_merge_keys<EM, W, PF>, lds);
     if (e != hipSuccess) return e;
     // persistent grid: as many workgroups as fit in the LDS of `grid` CUs
@@ -260,19 +270,18 @@ static hipError_t launch_variant(const uint32_t* src, uint32_t* dst, const Round
         lds_cu = 160 * 1024;
     const uint64_t per_cu = (uint64_t)lds_cu / lds > 0 ? (uint64_t)lds_cu / lds : 1;
     const uint64_t want = (uint64_t)grid * per_cu;
-    const unsigned blocks = (unsigned)(want < g.tiles ? want : g.tiles);
-    hipLaunchKernelGGL((k_merge_keys<EM, W, PF>), dim3(blocks), dim3(W * 64), lds, s, src, dst, g.n, g.L, g.K, g.Tout,
-                       g.tiles_per_group, g.tiles, table, flip_out);
+    const unsigned blocks = (unsigned)(want < ph.tiles ? want : ph.tiles);
+    hipLaunchKernelGGL((k_merge_keys<EM, W, PF>), dim3(blocks), dim3(W * 64), lds, s, ph, b, ra, table, flip);
     return hipGetLastError();
 }
 
-hipError_t launch_merge_keys(const uint32_t* src, uint32_t* dst, const RoundGeom& g, const uint32_t* table,
-                             uint32_t flip_out, unsigned grid, int variant, hipStream_t s) {
-    if (g.Tout > kToutKeys || g.K > kMaxFanout || g.Tout % 4 || g.L % 4) return hipErrorInvalidValue;
-    if (variant == 1) return launch_variant<8, 16>(src, dst, g, table, flip_out, grid, s);
-    if (variant == 2) return launch_variant<8, 8>(src, dst, g, table, flip_out, grid, s);
-    if (variant == 3) return launch_variant<16, 4>(src, dst, g, table, flip_out, grid, s);
-    return launch_variant<16, 8>(src, dst, g, table, flip_out, grid, s);
+hipError_t launch_merge_keys(const Phase& ph, const Bufs& b, const RoundArgs& ra, const uint32_t* table,
+                             uint32_t flip, unsigned grid, int variant, hipStream_t s) {
+    if (ra.Tout > kToutKeys || ra.K > kMaxFanout || ra.Tout % 4 || ra.L % 4) return hipErrorInvalidValue;
+    if (ph.tiles == 0) return hipSuccess;
+    if (variant == 1) return launch_variant<8, 16>(ph, b, ra, table, flip, grid, s);
+    if (variant == 2) return launch_variant<8, 8>(ph, b, ra, table, flip, grid, s);
+    return launch_variant<16, 8>(ph, b, ra, table, flip, grid, s);
 }
 
 }  // namespace mms

@@ -145,3 +145,39 @@ def test_last_error_is_per_thread(lib):
     t.join()
     assert seen["msg"] == b""
     assert lib.mms_last_error() != b""
+
+
+def test_segmented_workspace_and_errors(lib):
+    import numpy as np
+    off = np.array([0, 10, 10, 5000, 100_000], dtype=np.uint64)
+    ws = lib.mms_segmented_workspace_bytes(off.ctypes.data, 4, 0)
+    wsp = lib.mms_segmented_workspace_bytes(off.ctypes.data, 4, _lib.MMS_PAIRS)
+    assert ws >= 100_000 * 4 and wsp >= 2 * 100_000 * 4
+    bad = np.array([0, 10, 5], dtype=np.uint64)
+    assert lib.mms_segmented_workspace_bytes(bad.ctypes.data, 2, 0) == 0
+    # decreasing offsets are rejected before any device work
+    assert lib.mms_segmented_sort(FAKE, FAKE + 2**28, None, None, bad.ctypes.data, 2,
+                                  FAKE + 2**30, 1 << 20, 0, None) == _lib.MMS_EINVAL
+    assert b"decrease" in lib.mms_last_error()
+    # values need both sides
+    assert lib.mms_segmented_sort(FAKE, FAKE + 2**28, FAKE + 2**29, None, off.ctypes.data, 4,
+                                  FAKE + 2**30, 1 << 30, 0, None) == _lib.MMS_EINVAL
+    # zero segments is a no-op
+    assert lib.mms_segmented_sort(FAKE, FAKE, None, None, off.ctypes.data, 0, None, 0, 0, None) == 0
+
+
+def test_tuning_table(lib):
+    t = _lib.MmsTuning()
+    assert lib.mms_get_tuning(10**8, 0, t) == 0
+    default = (t.fanout, t.merge_tile, t.variant)
+    table = (_lib.MmsTuning * 2)(_lib.MmsTuning(20, 8, 4096, 1), _lib.MmsTuning(32, 16, 7168, 2))
+    assert lib.mms_set_tuning(table, 2) == 0
+    assert lib.mms_get_tuning(1 << 18, 0, t) == 0 and (t.fanout, t.merge_tile, t.variant) == (8, 4096, 1)
+    assert lib.mms_get_tuning(10**8, 0, t) == 0 and (t.fanout, t.merge_tile, t.variant) == (16, 7168, 2)
+    p = _lib.MmsPlan()
+    lib.mms_plan(1 << 18, 0, p)
+    assert p.fanout == 8 and p.rounds == expected_rounds(1 << 18, 2048, 8)
+    bad = (_lib.MmsTuning * 1)(_lib.MmsTuning(20, 3, 4096, 0))
+    assert lib.mms_set_tuning(bad, 1) == _lib.MMS_EINVAL
+    assert lib.mms_set_tuning(None, 0) == 0
+    assert lib.mms_get_tuning(10**8, 0, t) == 0 and (t.fanout, t.merge_tile, t.variant) == default
