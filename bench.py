@@ -13,8 +13,16 @@ buffer and written to another, workspace preallocated.  Prints one JSON line:
              changed since the counters were taken
   cpu_baseline  the CPU oracle (sequential heap-based mergesort, 1 thread)
              timed on a 2^25-key prefix of the same input
+  batched    4096 uint32 arrays, sizes log-uniform in [2^8, 2^20]: one
+             batched (segmented) sort vs 4096 plain calls on one stream
+  serving    a Poisson stream of requests (sizes log-uniform in [2^10, 2^26],
+             half keys-only, half pairs) at 70% of the measured saturated
+             throughput through the serving loop (64 GB arena), vs the same
+             trace served by a first-come first-served loop of plain calls:
+             p50/p99 latency and keys/s of each
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                       [--no-batched] [--no-serving]
 """
 from __future__ import annotations
 
@@ -32,7 +40,7 @@ N_KEYS = 10**8
 HBM_PEAK_GBS = 8000.0
 METRIC = "Gkeys/s sorting 1e8 uint32, % HBM roofline; p99 latency served vs per-call"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "merge_u32_1e8_traffic.json")
-KERNEL_SOURCES = ["paper_1702_07961_amd/csrc/mms_kernels.hip", "paper_1702_07961_amd/csrc/mms_device.h",
+KERNEL_SOURCES = ["paper_1702_07961_amd/csrc/mms_merge_keys.hip", "paper_1702_07961_amd/csrc/mms_device.h",
                   "paper_1702_07961_amd/csrc/mms_internal.h"]
 
 
@@ -68,6 +76,166 @@ def cpu_baseline(x_host):
                       f"5-way mergesort, {dt:.2f} s"}
 
 
+def bench_batched(mms, torch, np, mmsgen, reps: int = 5) -> dict:
+    """One batched sort of 4096 arrays vs 4096 plain calls (same stream)."""
+    import ctypes
+    sizes = mmsgen.loguniform_sizes(mmsgen.seed_for(4, 0), 4096, 8, 20).astype(np.int64)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    total = int(off[-1])
+    x = torch.from_numpy(mmsgen.uniform_u32(mmsgen.seed_for(4, 2), total).view(np.int32)).cuda()
+    out = torch.empty_like(x)
+    ws = torch.empty(mms.segmented_workspace_bytes(off), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    mms.segmented_sort(x, off, out_keys=out, workspace=ws, i32=False)     # captures the graph
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        mms.segmented_sort(x, off, out_keys=out, workspace=ws, i32=False)
+    b.record(stream)
+    torch.cuda.synchronize()
+    seg_ms = a.elapsed_time(b) / reps
+    seg_out = out.clone()
+
+    lib = mms._lib.lib()
+    wsp = torch.empty(max(mms.workspace_bytes(int(sizes.max())), 256), dtype=torch.uint8, device="cuda")
+    xp, op, wp, sp = x.data_ptr(), out.data_ptr(), wsp.data_ptr(), stream.cuda_stream
+    wbytes = wsp.numel()
+    calls = [(xp + 4 * int(o), op + 4 * int(o), int(n)) for o, n in zip(off[:-1], sizes)]
+
+    def plain_all():
+        for i_ptr, o_ptr, n in calls:
+            rc = lib.mms_sort_u32(i_ptr, o_ptr, n, wp, wbytes, 0, sp)
+            if rc:
+                mms._lib.check(rc)
+    plain_all()
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(2):
+        plain_all()
+    b.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = a.elapsed_time(b) / 2
+    if not torch.equal(seg_out, out):
+        raise RuntimeError("batched and plain results differ")
+    del ctypes
+    return {"workload": "4096 uint32 arrays, sizes log-uniform in [2^8, 2^20], uniform keys",
+            "total_keys": total,
+            "batched_ms": round(seg_ms, 3), "batched_gkeys_per_s": round(total / seg_ms / 1e6, 3),
+            "plain_calls_ms": round(plain_ms, 3), "plain_calls_gkeys_per_s": round(total / plain_ms / 1e6, 3),
+            "speedup": round(plain_ms / seg_ms, 3)}
+
+
+def _pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q))
+
+
+def bench_serving(mms, torch, np, mmsgen, count: int = 2100, warm: int = 100, rho: float = 0.7,
+                  arena_bytes: int = 64 << 30) -> dict:
+    """Continuous batching through the serving loop vs a per-call FIFO loop
+    on the same Poisson arrival trace."""
+    import queue
+    import threading
+    POOL = 1 << 26
+    pool_k = torch.from_numpy(mmsgen.uniform_u32(mmsgen.seed_for(5, 0), POOL).view(np.int32)).cuda()
+    pool_v = torch.arange(POOL, dtype=torch.int32, device="cuda")
+    sizes = mmsgen.loguniform_sizes(mmsgen.seed_for(5, 1), count, 10, 26).astype(np.int64)
+    pairs = mmsgen.unit_doubles(mmsgen.seed_for(5, 2), count) < 0.5
+    offs = (mmsgen.unit_doubles(mmsgen.seed_for(5, 3), count) * (POOL - sizes + 1)).astype(np.int64)
+    unit_arrivals = mmsgen.poisson_arrivals(mmsgen.seed_for(5, 4), count, 1.0)
+    torch.cuda.synchronize()
+
+    def req(i):
+        o, n = int(offs[i]), int(sizes[i])
+        return pool_k[o:o + n], (pool_v[o:o + n] if pairs[i] else None)
+
+    srv = mms.Server(budget_bytes=arena_bytes)
+    try:
+        # saturated throughput: a burst of requests submitted at once
+        burst = list(range(min(256, count)))
+        tk = [srv.submit(*req(i), stream=None) for i in burst]
+        rs = [srv.wait(t) for t in tk]
+        for t in tk:
+            srv.release(t)
+        x_sat = sum(int(sizes[i]) for i in burst) / (
+            (max(r.t_done_us for r in rs) - min(r.t_submit_us for r in rs)) * 1e-6)
+        mean_n = mmsgen.loguniform_mean(10, 26)
+        rate = rho * x_sat / mean_n
+        arrivals = unit_arrivals / rate
+
+        # served: a submitting thread on the arrival schedule, a collector thread
+        q = queue.Queue()
+        results = [None] * count
+        late = np.zeros(count)
+
+        def collect():
+            for _ in range(count):
+                i, t = q.get()
+                results[i] = srv.wait(t)
+                srv.release(t)
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        for i in range(count):
+            due = t0 + arrivals[i]
+            while True:
+                d = due - time.perf_counter()
+                if d <= 0:
+                    break
+                time.sleep(d if d > 2e-3 else 0)
+            q.put((i, srv.submit(*req(i), stream=None)))
+            late[i] = time.perf_counter() - due
+        th.join()
+        st = srv.stats()
+    finally:
+        srv.close()
+    meas = results[warm:]
+    lat = [(r.t_done_us - r.t_submit_us) / 1e3 for r in meas]
+    span_s = (max(r.t_done_us for r in meas) - min(r.t_submit_us for r in meas)) * 1e-6
+    keys = int(sizes[warm:].sum())
+    served = {"p50_ms": round(_pct(lat, 50), 3), "p99_ms": round(_pct(lat, 99), 3),
+              "gkeys_per_s": round(keys / span_s / 1e9, 3),
+              "mean_batch_requests": round(float(np.mean([r.batch_requests for r in meas])), 2),
+              "batches": int(st["batches"]), "peak_arena_GB": round(st["peak_used_bytes"] / 1e9, 2),
+              "submit_lateness_p99_ms": round(_pct(late[warm:] * 1e3, 99), 3)}
+
+    # per-call FIFO: one plain sort per request on one stream, in arrival order
+    nmax = int(sizes.max())
+    outk = torch.empty(nmax, dtype=torch.int32, device="cuda")
+    outv = torch.empty(nmax, dtype=torch.int32, device="cuda")
+    ws = torch.empty(max(mms.workspace_bytes(nmax, pairs=True), 256), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    done = np.zeros(count)
+    t0 = time.perf_counter()
+    for i in range(count):
+        due = t0 + arrivals[i]
+        while True:
+            d = due - time.perf_counter()
+            if d <= 0:
+                break
+            time.sleep(d if d > 2e-3 else 0)
+        k, v = req(i)
+        n = k.numel()
+        if v is None:
+            mms.sort(k, out=outk[:n], i32=False, workspace=ws, stream=stream)
+        else:
+            mms.sort_pairs(k, v, out_keys=outk[:n], out_values=outv[:n], i32=False, workspace=ws,
+                           stream=stream)
+        stream.synchronize()
+        done[i] = time.perf_counter() - t0
+    lat_pc = (done - arrivals)[warm:] * 1e3
+    pc_span = done[-1] - arrivals[warm]
+    per_call = {"p50_ms": round(_pct(lat_pc, 50), 3), "p99_ms": round(_pct(lat_pc, 99), 3),
+                "gkeys_per_s": round(keys / pc_span / 1e9, 3)}
+    return {"workload": "Poisson arrivals, sizes log-uniform in [2^10, 2^26], half keys-only uint32, "
+                        "half (uint32, uint32) pairs, 64 GB arena",
+            "requests": count - warm, "warmup_requests": warm, "offered_load": rho,
+            "saturated_gkeys_per_s": round(x_sat / 1e9, 3), "rate_per_s": round(rate, 1),
+            "served": served, "per_call_fifo": per_call,
+            "p99_per_call_over_served": round(per_call["p99_ms"] / served["p99_ms"], 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +243,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_KEYS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-sort comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sort runs on a single MI355X and this build "
@@ -166,6 +336,11 @@ def main():
     }
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(x_host)
+    del x, out, ws
+    if not args.no_batched:
+        rec["batched"] = bench_batched(mms, torch, np, mmsgen)
+    if not args.no_serving:
+        rec["serving"] = bench_serving(mms, torch, np, mmsgen)
     print(json.dumps(rec), flush=True)
 
 

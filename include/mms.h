@@ -170,6 +170,119 @@ int mms_set_tuning(const mms_tuning_t* entries, uint32_t count);
 int mms_get_tuning(uint64_t n, uint32_t flags, mms_tuning_t* out);
 
 /*
+ * Serving loop: a server owns a device arena (caller memory, e.g. a torch
+ * tensor), admits sort requests first-come first-served while the arena has
+ * room for them, and coalesces the admitted requests of one kind into
+ * batched sorts (the segmented sort's kernels, one launch per phase over all
+ * requests of the batch) on two or more streams, so that requests arriving
+ * while earlier ones run join the next batch and their work overlaps on the
+ * device.  Each result is the request sorted exactly as mms_sort_u32 /
+ * mms_sort_pairs_u32 would sort it alone (§4's problem statement; stable for
+ * pairs), and stays in the arena until mms_release.
+ *
+ * Memory: at creation the server reserves metadata slots (per-batch task
+ * lists and partition tables) at the start of the arena; the rest is the
+ * data budget.  A request of n elements needs 4n bytes for its result (8n
+ * for pairs) plus as much again of workspace while it runs (none when n fits
+ * one base-case tile), each rounded up to 256 bytes.  It is admitted when
+ * every earlier request has been admitted and both ranges fit; the workspace
+ * returns to the budget when its batch completes, the result on release.  A
+ * request that could never fit the data budget is refused at submission
+ * (MMS_ENOMEM).  The server calls no device allocator.
+ *
+ * Threads: a scheduler thread admits and launches; one completion thread per
+ * stream waits for the batches of its stream in order and stamps their
+ * requests.  Every call below is thread-safe except mms_server_destroy,
+ * which must not overlap any other call on the same server.
+ */
+#define MMS_SERVER_MAX_STREAMS 8
+#define MMS_SERVER_DRY_RUN 0x1u  /* run admission and completion with no device
+                                    work: results are not computed, the arena is
+                                    never dereferenced (scheduler tests) */
+
+typedef struct {
+    void* d_arena;              /* device buffer, 256-byte aligned, caller-owned  */
+    uint64_t arena_bytes;
+    void* streams[MMS_SERVER_MAX_STREAMS]; /* caller streams (hipStream_t); unused: NULL */
+    uint32_t num_streams;       /* 0: the server creates 2 non-blocking streams   */
+    uint32_t max_inflight;      /* batches enqueued and not complete, per stream (0: 2) */
+    uint32_t max_requests;      /* requests admitted and not released (0: 65536) */
+    uint32_t max_batch_requests;/* requests per batch (0: 1024)                  */
+    uint64_t max_batch_keys;    /* elements per batch, also the largest request (0: 2^28) */
+    uint32_t flags;             /* MMS_SERVER_DRY_RUN                             */
+    uint32_t reserved;
+} mms_server_cfg;
+
+typedef struct mms_server mms_server;
+
+typedef struct {
+    uint32_t flags;             /* MMS_PAIRS (values present), MMS_KEY_I32        */
+    uint32_t reserved;
+    uint64_t n;                 /* elements, 1 <= n <= max_batch_keys            */
+    const uint32_t* d_keys;     /* device input, caller-owned, unchanged          */
+    const uint32_t* d_vals;     /* device input values (MMS_PAIRS), else NULL     */
+    void* stream;               /* the input is read after the work enqueued on this
+                                   stream before mms_submit (NULL: the caller has
+                                   already synchronised it)                      */
+} mms_request;
+
+typedef struct {
+    int32_t status;             /* MMS_OK, MMS_PENDING or a negative status       */
+    uint32_t flags;
+    uint64_t n;
+    uint32_t* d_keys;           /* sorted keys inside the arena                   */
+    uint32_t* d_vals;           /* permuted values (pairs), else NULL             */
+    double t_submit_us;         /* host steady clock, µs since server creation    */
+    double t_admit_us;
+    double t_launch_us;
+    double t_done_us;           /* stamped by the completion thread               */
+    uint64_t batch;             /* sequence number of the batch it ran in         */
+    uint32_t batch_requests;    /* requests in that batch                         */
+    uint32_t stream_index;
+} mms_result;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, released, rejected, batches;
+    uint64_t queued;            /* waiting for admission                          */
+    uint64_t running;           /* admitted, not complete                         */
+    uint64_t data_budget_bytes; /* arena bytes available to requests              */
+    uint64_t used_bytes;        /* of which in use (results + workspaces)         */
+    uint64_t peak_used_bytes;
+    uint64_t meta_bytes;        /* arena bytes reserved for batch metadata        */
+    uint64_t max_batch_seen;    /* largest batch so far (requests)                */
+} mms_server_stats;
+
+/* Create a server.  Errors: MMS_EINVAL (arena, limits, streams), MMS_EHIP. */
+int mms_server_create(const mms_server_cfg* cfg, mms_server** out);
+
+/* Queue a request and return its ticket (> 0).  Errors: MMS_EINVAL (flags,
+ * n = 0, n > max_batch_keys, null pointers), MMS_ENOMEM (larger than the data
+ * budget), MMS_ESHUTDOWN (the server is being destroyed). */
+int mms_submit(mms_server* s, const mms_request* r, uint64_t* ticket);
+
+/* State of a ticket: MMS_PENDING while queued or running, MMS_OK with the
+ * result filled in when done, the request's error status if it failed,
+ * MMS_ENOENT for an unknown or released ticket. */
+int mms_poll(mms_server* s, uint64_t ticket, mms_result* out);
+
+/* mms_poll that blocks until the ticket is done or timeout_ms passes
+ * (negative: no limit); MMS_PENDING on timeout. */
+int mms_wait(mms_server* s, uint64_t ticket, int64_t timeout_ms, mms_result* out);
+
+/* Return a finished request's arena space.  With a non-NULL stream the space
+ * is reused only after the work enqueued on that stream so far (readers of
+ * the result) completes.  Errors: MMS_ENOENT (unknown or already released),
+ * MMS_EINVAL (still pending). */
+int mms_release(mms_server* s, uint64_t ticket, void* stream);
+
+int mms_server_get_stats(mms_server* s, mms_server_stats* out);
+
+/* Stop admitting (queued requests fail with MMS_ESHUTDOWN), wait for the
+ * batches in flight, join the threads and free the server.  Arena contents
+ * are left as they are. */
+int mms_server_destroy(mms_server* s);
+
+/*
  * Per-kernel timing, for measurement harnesses.  While enabled, every kernel
  * the library launches is bracketed by two hipEvents recorded on the stream
  * it is launched on, and mms_timing_read() waits for those events and

@@ -9,10 +9,11 @@ from __future__ import annotations
 
 from . import _lib
 from ._lib import MMS_KEY_I32, MMS_PAIRS, MmsError, MmsPlan  # noqa: F401
+from .server import Result, Server  # noqa: F401
 
 __all__ = ["sort", "sort_pairs", "partition", "copy", "plan", "workspace_bytes", "MmsError",
            "timing_enable", "timing_reset", "timing_read", "segmented_sort", "segmented_workspace_bytes",
-           "set_tuning", "get_tuning"]
+           "set_tuning", "get_tuning", "Server", "Result"]
 
 
 def _torch():

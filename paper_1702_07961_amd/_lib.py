@@ -28,8 +28,12 @@ EXPORTS = [
     "mms_last_error", "mms_version", "mms_plan", "mms_workspace_bytes", "mms_sort_u32",
     "mms_sort_pairs_u32", "mms_partition_u32", "mms_copy_u32", "mms_timing_enable",
     "mms_timing_reset", "mms_timing_read", "mms_segmented_workspace_bytes", "mms_segmented_sort",
-    "mms_set_tuning", "mms_get_tuning",
+    "mms_set_tuning", "mms_get_tuning", "mms_server_create", "mms_submit", "mms_poll", "mms_wait",
+    "mms_release", "mms_server_get_stats", "mms_server_destroy",
 ]
+
+MMS_SERVER_MAX_STREAMS = 8
+MMS_SERVER_DRY_RUN = 0x1
 
 KERNEL_KINDS = ["tile_sort", "partition", "merge", "copy", "segmented"]
 
@@ -66,6 +70,55 @@ class MmsTuning(ctypes.Structure):
         ("merge_tile", ctypes.c_uint32),
         ("variant", ctypes.c_uint32),
     ]
+
+
+class MmsServerCfg(ctypes.Structure):
+    _fields_ = [
+        ("d_arena", ctypes.c_void_p),
+        ("arena_bytes", ctypes.c_uint64),
+        ("streams", ctypes.c_void_p * 8),
+        ("num_streams", ctypes.c_uint32),
+        ("max_inflight", ctypes.c_uint32),
+        ("max_requests", ctypes.c_uint32),
+        ("max_batch_requests", ctypes.c_uint32),
+        ("max_batch_keys", ctypes.c_uint64),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class MmsRequest(ctypes.Structure):
+    _fields_ = [
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("n", ctypes.c_uint64),
+        ("d_keys", ctypes.c_void_p),
+        ("d_vals", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class MmsResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("n", ctypes.c_uint64),
+        ("d_keys", ctypes.c_void_p),
+        ("d_vals", ctypes.c_void_p),
+        ("t_submit_us", ctypes.c_double),
+        ("t_admit_us", ctypes.c_double),
+        ("t_launch_us", ctypes.c_double),
+        ("t_done_us", ctypes.c_double),
+        ("batch", ctypes.c_uint64),
+        ("batch_requests", ctypes.c_uint32),
+        ("stream_index", ctypes.c_uint32),
+    ]
+
+
+class MmsServerStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in (
+        "submitted", "admitted", "completed", "released", "rejected", "batches", "queued", "running",
+        "data_budget_bytes", "used_bytes", "peak_used_bytes", "meta_bytes", "max_batch_seen")]
 
 
 class MmsError(RuntimeError):
@@ -107,6 +160,20 @@ def _declare(lib):
     lib.mms_set_tuning.restype = ctypes.c_int
     lib.mms_get_tuning.argtypes = [_u64, _u32, ctypes.POINTER(MmsTuning)]
     lib.mms_get_tuning.restype = ctypes.c_int
+    lib.mms_server_create.argtypes = [ctypes.POINTER(MmsServerCfg), ctypes.POINTER(_vp)]
+    lib.mms_server_create.restype = ctypes.c_int
+    lib.mms_submit.argtypes = [_vp, ctypes.POINTER(MmsRequest), ctypes.POINTER(_u64)]
+    lib.mms_submit.restype = ctypes.c_int
+    lib.mms_poll.argtypes = [_vp, _u64, ctypes.POINTER(MmsResult)]
+    lib.mms_poll.restype = ctypes.c_int
+    lib.mms_wait.argtypes = [_vp, _u64, ctypes.c_int64, ctypes.POINTER(MmsResult)]
+    lib.mms_wait.restype = ctypes.c_int
+    lib.mms_release.argtypes = [_vp, _u64, _vp]
+    lib.mms_release.restype = ctypes.c_int
+    lib.mms_server_get_stats.argtypes = [_vp, ctypes.POINTER(MmsServerStats)]
+    lib.mms_server_get_stats.restype = ctypes.c_int
+    lib.mms_server_destroy.argtypes = [_vp]
+    lib.mms_server_destroy.restype = ctypes.c_int
     return lib
 
 

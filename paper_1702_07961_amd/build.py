@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmms.so")
 
-SOURCES = ["mms_kernels.hip", "mms_merge_keys.hip", "mms_api.cpp"]
+SOURCES = ["mms_kernels.hip", "mms_merge_keys.hip", "mms_api.cpp", "mms_server.cpp"]
 ARCH = "gfx950"
 
 COMMON = [

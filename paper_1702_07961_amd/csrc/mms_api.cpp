@@ -17,11 +17,17 @@
 #include <vector>
 
 #include "mms.h"
+#include "mms_host.h"
 #include "mms_internal.h"
 
-namespace {
+namespace mms {
+namespace host {
 
+namespace {
 thread_local std::string g_err;
+}
+
+const char* last_error() { return g_err.c_str(); }
 
 int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -36,6 +42,7 @@ int fail(int code, const char* fmt, ...) {
 int hip_fail(hipError_t e, const char* what) { return fail(MMS_EHIP, "%s: %s", what, hipGetErrorString(e)); }
 
 // ---- per-kernel timing (mms_timing_*) --------------------------------------
+namespace {
 struct TimingRec {
     int kind;
     hipEvent_t a, b;
@@ -58,43 +65,33 @@ hipEvent_t take_event() {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
+}  // namespace
 
-// Brackets one kernel launch (or graph launch) with events on its stream
-// when timing is on.
-class Timed {
-  public:
-    Timed(int kind, hipStream_t s) : kind_(kind), s_(s) {
-        if (g_capturing) return;
-        std::lock_guard<std::mutex> g(g_tmu);
-        if (!g_timing) return;
-        a_ = take_event();
-        b_ = take_event();
-        if (a_ && b_) hipEventRecord(a_, s_);
-    }
-    ~Timed() {
-        if (!a_ || !b_) return;
-        hipEventRecord(b_, s_);
-        std::lock_guard<std::mutex> g(g_tmu);
-        g_recs.push_back({kind_, a_, b_});
-    }
+void set_capturing(bool on) { g_capturing = on; }
 
-  private:
-    int kind_;
-    hipStream_t s_;
-    hipEvent_t a_ = nullptr, b_ = nullptr;
-};
+Timed::Timed(int kind, hipStream_t s) : kind_(kind), s_(s) {
+    if (g_capturing) return;
+    std::lock_guard<std::mutex> g(g_tmu);
+    if (!g_timing) return;
+    a_ = take_event();
+    b_ = take_event();
+    if (a_ && b_) (void)hipEventRecord(a_, s_);
+}
+
+Timed::~Timed() {
+    if (!a_ || !b_) return;
+    (void)hipEventRecord(b_, s_);
+    std::lock_guard<std::mutex> g(g_tmu);
+    g_recs.push_back({kind_, a_, b_});
+}
 
 // ---- tuning ------------------------------------------------------------------
 // Ordered by max_log2_n; a sort of n uses the first entry with
 // ceil(log2 n) <= max_log2_n (the last entry otherwise).
+namespace {
 std::mutex g_tune_mu;
 std::vector<mms_tuning_t> g_tuning;
-
-struct Tune {
-    uint32_t K;
-    uint32_t Tout;
-    int variant;
-};
+}  // namespace
 
 uint32_t ceil_log2(uint64_t n) {
     uint32_t l = 0;
@@ -144,15 +141,108 @@ unsigned persistent_grid() {
     return (unsigned)cus;
 }
 
-constexpr uint64_t kAlign = 256;
-uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+// ---- the phase loop ----------------------------------------------------------
+namespace {
+struct PhaseList {
+    Phase base;                    // base-case pass
+    std::vector<Phase> rounds;     // merge rounds
+};
 
-// §6.2: ceil(log_K(ceil(n / T))) merge rounds after the base case.
-uint32_t rounds_for(uint64_t n, uint32_t T, uint32_t K) {
-    uint32_t r = 0;
-    for (uint64_t L = T; L < n; L *= K) ++r;
-    return r;
+int run_phases(bool pairs, const PhaseList& pl, const Bufs& b, uint32_t* table, const Tune& tune, uint32_t flip,
+               hipStream_t s) {
+    hipError_t e;
+    {
+        Timed tm(MMS_KERNEL_TILE_SORT, s);
+        e = launch_tile_sort(pairs, pl.base, b, flip, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "tile sort launch");
+    uint64_t L = kT1;
+    for (size_t r = 0; r < pl.rounds.size(); ++r, L *= tune.K) {
+        const Phase& ph = pl.rounds[r];
+        if (ph.tiles == 0) continue;
+        const RoundArgs ra{L, tune.K, tune.Tout, (L * tune.K + tune.Tout - 1) / tune.Tout};
+        {
+            Timed tm(MMS_KERNEL_PARTITION, s);
+            e = launch_corank_tiles(ph, b, ra, table, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "partition launch");
+        {
+            Timed tm(MMS_KERNEL_MERGE, s);
+            if (pairs) e = launch_merge_pairs(ph, b, ra, table, flip, s);
+            else e = launch_merge_keys(ph, b, ra, table, flip, persistent_grid(), tune.variant, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "merge launch");
+    }
+    return MMS_OK;
 }
+}  // namespace
+
+// ---- batches -------------------------------------------------------------------
+void build_batch_tasks(const uint64_t* seg_n, uint64_t ns, bool pairs, const Tune& tune, BatchTasks& bt) {
+    bt.pairs = pairs;
+    bt.tune = tune;
+    bt.phases.assign(1, {});
+    bt.max_round_tiles = 0;
+    bt.ntasks = 0;
+    const uint32_t T = kT1, K = tune.K;
+    for (uint64_t s = 0; s < ns; ++s) {
+        const uint64_t n = seg_n[s];
+        if (n == 0) continue;
+        const uint32_t R = rounds_for(n, T, K);
+        if (bt.phases.size() < (size_t)R + 1) bt.phases.resize(R + 1);
+        const uint32_t base_info = ((R % 2 == 0) ? kTaskDstOut : 0u) | (R == 0 ? kTaskFinal : 0u);
+        for (uint64_t t = 0; t * T < n; ++t) bt.phases[0].push_back({(uint32_t)s, (uint32_t)t | base_info});
+        uint64_t L = T;
+        for (uint32_t r = 0; r < R; ++r, L *= K) {
+            const RoundGeom g = round_geom(n, L, K, tune.Tout);
+            const uint32_t info = (((R - r - 1) % 2 == 0) ? kTaskDstOut : 0u) | (r + 1 == R ? kTaskFinal : 0u);
+            for (uint64_t t = 0; t < g.tiles; ++t) bt.phases[1 + r].push_back({(uint32_t)s, (uint32_t)t | info});
+        }
+    }
+    for (size_t r = 0; r < bt.phases.size(); ++r) {
+        bt.ntasks += bt.phases[r].size();
+        if (r) bt.max_round_tiles = std::max<uint64_t>(bt.max_round_tiles, bt.phases[r].size());
+    }
+}
+
+// With T = 2048, K >= 2 and Tout >= 1024: a segment of n elements has at
+// most n/2048 + 1 base tiles and, per round, at most n/1024 tiles plus one
+// per group (n/4096 + 1 groups); it has at most rounds_for(n, 2048, 2) rounds.
+static uint64_t round_tiles_bound(uint64_t total, uint64_t ns) { return (5 * total) / 4096 + 2 * ns + 1; }
+
+uint64_t batch_tasks_bound(uint64_t total, uint64_t ns) {
+    return total / kT1 + ns + 1 + (uint64_t)rounds_for(total, kT1, 2) * round_tiles_bound(total, ns);
+}
+
+uint64_t batch_table_bound(uint64_t total, uint64_t ns) {
+    return align_up((round_tiles_bound(total, ns) + 1) * kMaxFanout * 4);
+}
+
+int run_batch(const BatchTasks& bt, const SegDesc* d_segs, const TileTask* d_tasks, uint32_t* table, uint32_t flip,
+              hipStream_t s) {
+    PhaseList pl;
+    size_t at = 0;
+    for (size_t i = 0; i < bt.phases.size(); ++i) {
+        const Phase ph{d_tasks + at, d_segs, 0, 0, 0, bt.phases[i].size()};
+        if (i == 0) pl.base = ph;
+        else pl.rounds.push_back(ph);
+        at += bt.phases[i].size();
+    }
+    return run_phases(bt.pairs, pl, Bufs{}, table, bt.tune, flip, s);
+}
+
+int run_plain(bool pairs, const Phase& base, const std::vector<Phase>& rounds, const Bufs& b, uint32_t* table,
+              const Tune& tune, uint32_t flip, hipStream_t s) {
+    PhaseList pl{base, rounds};
+    return run_phases(pairs, pl, b, table, tune, flip, s);
+}
+
+}  // namespace host
+}  // namespace mms
+
+using namespace mms::host;
+
+namespace {
 
 // ---- plain sort plan ---------------------------------------------------------
 struct Plan {
@@ -218,40 +308,6 @@ int check_buffers(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint
     return MMS_OK;
 }
 
-// ---- the phase loop ----------------------------------------------------------
-struct PhaseList {
-    mms::Phase base;                    // base-case pass
-    std::vector<mms::Phase> rounds;     // merge rounds
-};
-
-int run_phases(bool pairs, const PhaseList& pl, const mms::Bufs& b, uint32_t* table, const Tune& tune,
-               uint32_t flip, hipStream_t s) {
-    hipError_t e;
-    {
-        Timed tm(MMS_KERNEL_TILE_SORT, s);
-        e = mms::launch_tile_sort(pairs, pl.base, b, flip, s);
-    }
-    if (e != hipSuccess) return hip_fail(e, "tile sort launch");
-    uint64_t L = mms::kT1;
-    for (size_t r = 0; r < pl.rounds.size(); ++r, L *= tune.K) {
-        const mms::Phase& ph = pl.rounds[r];
-        if (ph.tiles == 0) continue;
-        const mms::RoundArgs ra{L, tune.K, tune.Tout, (L * tune.K + tune.Tout - 1) / tune.Tout};
-        {
-            Timed tm(MMS_KERNEL_PARTITION, s);
-            e = mms::launch_corank_tiles(ph, b, ra, table, s);
-        }
-        if (e != hipSuccess) return hip_fail(e, "partition launch");
-        {
-            Timed tm(MMS_KERNEL_MERGE, s);
-            if (pairs) e = mms::launch_merge_pairs(ph, b, ra, table, flip, s);
-            else e = mms::launch_merge_keys(ph, b, ra, table, flip, persistent_grid(), tune.variant, s);
-        }
-        if (e != hipSuccess) return hip_fail(e, "merge launch");
-    }
-    return MMS_OK;
-}
-
 int sort_impl(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint64_t n, void* ws,
               size_t ws_bytes, uint32_t flags, void* stream) {
     const bool pairs = vin != nullptr;
@@ -265,28 +321,30 @@ int sort_impl(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t
     mms::Bufs b{kin, vin, kout, vout, (uint32_t*)wsb, pairs ? (uint32_t*)(wsb + p.off_vals) : nullptr};
     uint32_t* table = p.rounds ? (uint32_t*)(wsb + p.off_table) : nullptr;
     // pass i writes the output when R - i is even, so pass R lands there
-    PhaseList pl;
-    pl.base = mms::Phase{nullptr, n, (p.rounds % 2 == 0) ? 1u : 0u, p.rounds == 0 ? 1u : 0u, (n + p.T - 1) / p.T};
+    const mms::Phase base{nullptr, nullptr, n, (p.rounds % 2 == 0) ? 1u : 0u, p.rounds == 0 ? 1u : 0u,
+                          (n + p.T - 1) / p.T};
+    std::vector<mms::Phase> rounds;
     uint64_t L = p.T;
     for (uint32_t r = 0; r < p.rounds; ++r, L *= p.tune.K) {
         const mms::RoundGeom g = mms::round_geom(n, L, p.tune.K, p.tune.Tout);
-        pl.rounds.push_back(
-            mms::Phase{nullptr, n, ((p.rounds - r - 1) % 2 == 0) ? 1u : 0u, r + 1 == p.rounds ? 1u : 0u, g.tiles});
+        rounds.push_back(mms::Phase{nullptr, nullptr, n, ((p.rounds - r - 1) % 2 == 0) ? 1u : 0u,
+                                    r + 1 == p.rounds ? 1u : 0u, g.tiles});
     }
-    return run_phases(pairs, pl, b, table, p.tune, (flags & MMS_KEY_I32) ? 0x80000000u : 0u, (hipStream_t)stream);
+    return run_plain(pairs, base, rounds, b, table, p.tune, (flags & MMS_KEY_I32) ? 0x80000000u : 0u,
+                     (hipStream_t)stream);
 }
 
 // ---- segmented batch -----------------------------------------------------------
 // Every segment is sorted as its own plain sort; each phase's tiles of all
 // segments form one task list, so the batch runs one launch per kernel and
-// phase.  Segment s needs R_s rounds; its pass i writes the output when
-// R_s - i is even.
+// phase.  The workspace mirrors the arrays: segment s uses
+// ws[h_offsets[s] .. h_offsets[s+1]) for keys (and the values region likewise).
 struct SegPlan {
     bool pairs;
-    Tune tune;
-    uint64_t total;                              // elements covered (h_offsets[num_segs])
-    std::vector<std::vector<mms::TileTask>> tasks;   // [0] base case, [1 + r] round r
-    uint64_t max_round_tiles;
+    uint64_t total;                    // h_offsets[num_segs]
+    std::vector<uint64_t> seg_off;     // non-empty segments
+    std::vector<uint64_t> seg_n;
+    BatchTasks bt;
     uint64_t off_vals, off_table, ws_bytes;
 };
 
@@ -294,43 +352,32 @@ int make_seg_plan(const uint64_t* off, uint64_t ns, uint32_t flags, SegPlan& sp)
     sp.pairs = (flags & MMS_PAIRS) != 0;
     sp.total = off[ns];
     uint64_t maxn = 0;
+    sp.seg_off.clear();
+    sp.seg_n.clear();
     for (uint64_t s = 0; s < ns; ++s) {
         if (off[s + 1] < off[s]) return fail(MMS_EINVAL, "offsets decrease at segment %llu", (unsigned long long)s);
-        maxn = std::max<uint64_t>(maxn, off[s + 1] - off[s]);
-    }
-    if (maxn >= (1ull << 32)) return fail(MMS_EINVAL, "a segment holds 2^32 or more elements");
-    sp.tune = tune_for(maxn ? maxn : 1, sp.pairs);
-    const uint32_t T = mms::kT1, K = sp.tune.K;
-    sp.tasks.assign(1, {});
-    sp.max_round_tiles = 0;
-    for (uint64_t s = 0; s < ns; ++s) {
         const uint64_t n = off[s + 1] - off[s];
-        if (n == 0) continue;
-        const uint32_t R = rounds_for(n, T, K);
-        if (sp.tasks.size() < (size_t)R + 1) sp.tasks.resize(R + 1);
-        const uint32_t base_info = ((R % 2 == 0) ? mms::kTaskDstOut : 0u) | (R == 0 ? mms::kTaskFinal : 0u);
-        for (uint64_t t = 0; t * T < n; ++t) sp.tasks[0].push_back({off[s], (uint32_t)n, (uint32_t)t | base_info});
-        uint64_t L = T;
-        for (uint32_t r = 0; r < R; ++r, L *= K) {
-            const mms::RoundGeom g = mms::round_geom(n, L, K, sp.tune.Tout);
-            const uint32_t info = (((R - r - 1) % 2 == 0) ? mms::kTaskDstOut : 0u) | (r + 1 == R ? mms::kTaskFinal : 0u);
-            for (uint64_t t = 0; t < g.tiles; ++t) sp.tasks[1 + r].push_back({off[s], (uint32_t)n, (uint32_t)t | info});
+        maxn = std::max<uint64_t>(maxn, n);
+        if (n) {
+            sp.seg_off.push_back(off[s]);
+            sp.seg_n.push_back(n);
         }
     }
-    for (size_t r = 1; r < sp.tasks.size(); ++r)
-        sp.max_round_tiles = std::max<uint64_t>(sp.max_round_tiles, sp.tasks[r].size());
+    if (maxn >= (1ull << 32)) return fail(MMS_EINVAL, "a segment holds 2^32 or more elements");
+    build_batch_tasks(sp.seg_n.data(), sp.seg_n.size(), sp.pairs, tune_for(maxn ? maxn : 1, sp.pairs), sp.bt);
     sp.off_vals = align_up(sp.total * 4);
     sp.off_table = sp.off_vals + (sp.pairs ? align_up(sp.total * 4) : 0);
-    sp.ws_bytes = sp.off_table + align_up((sp.max_round_tiles + 1) * K * 4);
+    sp.ws_bytes = sp.off_table + sp.bt.table_bytes();
     return MMS_OK;
 }
 
-// A captured batch: task lists in device memory owned by the library and the
-// instantiated graph of all launches, keyed by offsets, pointers and tuning.
+// A captured batch: SegDesc table and task lists in device memory owned by
+// the library, and the instantiated graph of all launches, keyed by
+// offsets, pointers and tuning.
 struct SegEntry {
     std::string key;
     SegPlan plan;
-    mms::TileTask* d_tasks = nullptr;
+    void* d_meta = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
 };
@@ -340,12 +387,12 @@ std::list<SegEntry> g_seg_cache;   // most recent first
 constexpr size_t kSegCacheMax = 8;
 
 void drop_entry(SegEntry& e) {
-    if (e.exec) hipGraphExecDestroy(e.exec);
-    if (e.graph) hipGraphDestroy(e.graph);
-    if (e.d_tasks) hipFree(e.d_tasks);
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+    if (e.d_meta) (void)hipFree(e.d_meta);
     e.exec = nullptr;
     e.graph = nullptr;
-    e.d_tasks = nullptr;
+    e.d_meta = nullptr;
 }
 
 std::string seg_key(const uint64_t* off, uint64_t ns, uint32_t flags, const void* const* ptrs, int nptr,
@@ -377,32 +424,42 @@ int segmented_impl(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uin
     SegPlan sp;
     int rc = make_seg_plan(off, ns, flags | (pairs ? MMS_PAIRS : 0u), sp);
     if (rc) return rc;
-    if (sp.total == 0) return MMS_OK;
+    if (sp.seg_n.empty()) return MMS_OK;
     rc = check_buffers(kin, vin, kout, vout, sp.total, ws, sp.ws_bytes, ws_bytes);
     if (rc) return rc;
 
     const void* ptrs[5] = {kin, kout, vin, vout, ws};
-    const std::string key = seg_key(off, ns, flags | (pairs ? MMS_PAIRS : 0u), ptrs, 5, sp.tune);
+    const std::string key = seg_key(off, ns, flags | (pairs ? MMS_PAIRS : 0u), ptrs, 5, sp.bt.tune);
     std::lock_guard<std::mutex> lock(g_seg_mu);
     auto it = std::find_if(g_seg_cache.begin(), g_seg_cache.end(), [&](const SegEntry& e) { return e.key == key; });
     if (it == g_seg_cache.end()) {
         SegEntry e;
         e.key = key;
         e.plan = std::move(sp);
-        size_t ntasks = 0;
-        for (auto& v : e.plan.tasks) ntasks += v.size();
-        hipError_t he = hipMalloc(&e.d_tasks, std::max<size_t>(ntasks, 1) * sizeof(mms::TileTask));
+        const SegPlan& p = e.plan;
+        uint8_t* wsb = (uint8_t*)ws;
+        uint32_t* ws_k = (uint32_t*)wsb;
+        uint32_t* ws_v = pairs ? (uint32_t*)(wsb + p.off_vals) : nullptr;
+        // host image of the device metadata: SegDesc table, then the tasks
+        const uint64_t seg_bytes = align_up(p.seg_n.size() * sizeof(mms::SegDesc));
+        std::vector<uint8_t> img(seg_bytes + p.bt.ntasks * sizeof(mms::TileTask));
+        mms::SegDesc* sd = (mms::SegDesc*)img.data();
+        for (size_t i = 0; i < p.seg_n.size(); ++i) {
+            const uint64_t o = p.seg_off[i];
+            sd[i] = mms::SegDesc{kin + o, pairs ? vin + o : nullptr, kout + o, pairs ? vout + o : nullptr,
+                                 ws_k + o, pairs ? ws_v + o : nullptr, p.seg_n[i], 0};
+        }
+        size_t at = seg_bytes;
+        for (auto& v : p.bt.phases) {
+            if (!v.empty()) memcpy(img.data() + at, v.data(), v.size() * sizeof(mms::TileTask));
+            at += v.size() * sizeof(mms::TileTask);
+        }
+        hipError_t he = hipMalloc(&e.d_meta, img.size());
         if (he != hipSuccess) return fail(MMS_ENOMEM, "task list allocation: %s", hipGetErrorString(he));
-        size_t at = 0;
-        for (auto& v : e.plan.tasks) {
-            if (!v.empty()) {
-                he = hipMemcpy(e.d_tasks + at, v.data(), v.size() * sizeof(mms::TileTask), hipMemcpyHostToDevice);
-                if (he != hipSuccess) {
-                    drop_entry(e);
-                    return hip_fail(he, "task list upload");
-                }
-            }
-            at += v.size();
+        he = hipMemcpy(e.d_meta, img.data(), img.size(), hipMemcpyHostToDevice);
+        if (he != hipSuccess) {
+            drop_entry(e);
+            return hip_fail(he, "task list upload");
         }
         g_seg_cache.push_front(std::move(e));
         while (g_seg_cache.size() > kSegCacheMax) {
@@ -416,19 +473,12 @@ int segmented_impl(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uin
     }
     SegEntry& e = *it;
     const SegPlan& p = e.plan;
-    uint8_t* wsb = (uint8_t*)ws;
-    mms::Bufs b{kin, vin, kout, vout, (uint32_t*)wsb, pairs ? (uint32_t*)(wsb + p.off_vals) : nullptr};
-    uint32_t* table = (uint32_t*)(wsb + p.off_table);
-    PhaseList pl;
-    size_t at = 0;
-    for (size_t i = 0; i < p.tasks.size(); ++i) {
-        const mms::Phase ph{e.d_tasks + at, 0, 0, 0, p.tasks[i].size()};
-        if (i == 0) pl.base = ph;
-        else pl.rounds.push_back(ph);
-        at += p.tasks[i].size();
-    }
+    const mms::SegDesc* d_segs = (const mms::SegDesc*)e.d_meta;
+    const mms::TileTask* d_tasks =
+        (const mms::TileTask*)((uint8_t*)e.d_meta + align_up(p.seg_n.size() * sizeof(mms::SegDesc)));
+    uint32_t* table = (uint32_t*)((uint8_t*)ws + p.off_table);
     const uint32_t flip = (flags & MMS_KEY_I32) ? 0x80000000u : 0u;
-    if (!seg_graph_enabled()) return run_phases(pairs, pl, b, table, p.tune, flip, s);
+    if (!seg_graph_enabled()) return run_batch(p.bt, d_segs, d_tasks, table, flip, s);
 
     if (!e.exec) {
         hipStream_t cap = nullptr;
@@ -436,23 +486,23 @@ int segmented_impl(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uin
         if (he != hipSuccess) return hip_fail(he, "capture stream");
         he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (he != hipSuccess) {
-            hipStreamDestroy(cap);
+            (void)hipStreamDestroy(cap);
             return hip_fail(he, "begin capture");
         }
-        g_capturing = true;
-        rc = run_phases(pairs, pl, b, table, p.tune, flip, cap);
-        g_capturing = false;
+        set_capturing(true);
+        rc = run_batch(p.bt, d_segs, d_tasks, table, flip, cap);
+        set_capturing(false);
         hipGraph_t graph = nullptr;
         he = hipStreamEndCapture(cap, &graph);
-        hipStreamDestroy(cap);
+        (void)hipStreamDestroy(cap);
         if (rc) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             return rc;
         }
         if (he != hipSuccess) return hip_fail(he, "end capture");
         he = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
         if (he != hipSuccess) {
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);
             return hip_fail(he, "graph instantiate");
         }
         e.graph = graph;
@@ -470,7 +520,7 @@ int segmented_impl(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uin
 
 extern "C" {
 
-const char* mms_last_error(void) { return g_err.c_str(); }
+const char* mms_last_error(void) { return last_error(); }
 
 int mms_version(void) { return 200; }
 
@@ -512,7 +562,7 @@ size_t mms_segmented_workspace_bytes(const uint64_t* h_offsets, uint64_t num_seg
     if (!h_offsets || num_segs == 0) return 0;
     SegPlan sp;
     if (make_seg_plan(h_offsets, num_segs, flags, sp)) return 0;
-    return sp.total ? (size_t)sp.ws_bytes : 0;
+    return sp.seg_n.empty() ? 0 : (size_t)sp.ws_bytes;
 }
 
 int mms_segmented_sort(const uint32_t* d_kin, uint32_t* d_kout, const uint32_t* d_vin, uint32_t* d_vout,
@@ -588,7 +638,7 @@ int mms_timing_enable(int on) {
 int mms_timing_reset(void) {
     std::lock_guard<std::mutex> g(g_tmu);
     for (auto& r : g_recs) {
-        hipEventSynchronize(r.b);
+        (void)hipEventSynchronize(r.b);
         g_pool.push_back(r.a);
         g_pool.push_back(r.b);
     }

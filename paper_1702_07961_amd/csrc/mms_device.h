@@ -301,6 +301,11 @@ template <> struct Xpose<8> {
 // compiler and LDS ordering point for a wave's own scratch traffic
 __device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
+// Workgroup barrier for LDS traffic only.  Unlike __syncthreads() it does not
+// wait for outstanding global loads and stores, so a prefetch into registers
+// and the previous tile's stores stay in flight across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 __device__ __forceinline__ void cex_u32(uint32_t& lo, uint32_t& hi) {
     const uint32_t a = lo, b = hi;
     lo = min(a, b);

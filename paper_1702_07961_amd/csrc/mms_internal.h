@@ -19,12 +19,25 @@ constexpr uint32_t kToutKeys = 8192;   // largest keys-only merge tile
 constexpr uint32_t kToutPairs = 4096;
 constexpr uint32_t kMaxFanout = 16;
 
-// One tile of a phase (base case or merge round).  A batch of segments is a
-// list of such tiles; the plain sort is the one-segment case and needs no
-// list.  Within a segment every position is relative to `base`.
+// The buffers of one segment: its input, its output and its ping-pong
+// workspace (values null for keys-only sorts).  The plain sort is a single
+// segment described by the kernel's Bufs argument; a batch gives every
+// segment its own pointers, so segments need not share arrays.
+struct SegDesc {
+    const uint32_t* in_k;
+    const uint32_t* in_v;
+    uint32_t* out_k;
+    uint32_t* out_v;
+    uint32_t* ws_k;
+    uint32_t* ws_v;
+    uint64_t n;        // segment length (< 2^32)
+    uint64_t pad;
+};
+static_assert(sizeof(SegDesc) == 64, "SegDesc is one 64-byte record");
+
+// One tile of a phase (base case or merge round) of a batch.
 struct TileTask {
-    uint64_t base;    // first element of the segment in the arrays
-    uint32_t n;       // segment length
+    uint32_t seg;     // index into the batch's SegDesc table
     uint32_t info;    // bits 0..27 tile index inside the segment's phase,
                       // bit 30: the pass writes the output (else the workspace),
                       // bit 31: last pass of the segment (undo the int32 flip)
@@ -33,31 +46,7 @@ constexpr uint32_t kTaskTileMask = 0x0FFFFFFFu;
 constexpr uint32_t kTaskDstOut = 1u << 30;
 constexpr uint32_t kTaskFinal = 1u << 31;
 
-// A phase: either an explicit task list, or one segment [0, n) whose tiles
-// all share dst_out / final.
-struct Phase {
-    const TileTask* tasks;
-    uint64_t n;
-    uint32_t dst_out;
-    uint32_t final_pass;
-    uint64_t tiles;
-};
-
-// Device view of tile t of a phase.
-struct TileRef {
-    uint64_t base;     // segment start
-    uint64_t n;        // segment length
-    uint32_t local;    // tile index inside the segment's phase
-    bool dst_out;
-    bool final_pass;
-};
-__device__ __forceinline__ TileRef tile_ref(const Phase& ph, uint64_t t) {
-    if (!ph.tasks) return {0, ph.n, (uint32_t)t, ph.dst_out != 0, ph.final_pass != 0};
-    const TileTask tk = ph.tasks[t];
-    return {tk.base, tk.n, tk.info & kTaskTileMask, (tk.info & kTaskDstOut) != 0, (tk.info & kTaskFinal) != 0};
-}
-
-// The two ping-pong buffers of a sort (output and workspace) plus its input.
+// The buffers of a plain (single-segment) sort.
 struct Bufs {
     const uint32_t* in_k;
     const uint32_t* in_v;
@@ -66,6 +55,61 @@ struct Bufs {
     uint32_t* ws_k;
     uint32_t* ws_v;
 };
+
+// A phase: either an explicit task list over a SegDesc table, or one segment
+// [0, n) in Bufs whose tiles all share dst_out / final.
+struct Phase {
+    const TileTask* tasks;
+    const SegDesc* segs;
+    uint64_t n;
+    uint32_t dst_out;
+    uint32_t final_pass;
+    uint64_t tiles;
+};
+
+// Device view of tile t of a phase: its segment's buffers already resolved
+// to the one this pass reads (src) and the one it writes (dst).
+struct TileRef {
+    const uint32_t* in_k;   // segment input (base case)
+    const uint32_t* in_v;
+    const uint32_t* src_k;  // buffer a merge round reads
+    const uint32_t* src_v;
+    uint32_t* dst_k;        // buffer the pass writes
+    uint32_t* dst_v;
+    uint64_t n;             // segment length
+    uint32_t local;         // tile index inside the segment's phase
+    bool final_pass;
+};
+__device__ __forceinline__ TileRef tile_ref(const Phase& ph, const Bufs& b, uint64_t t) {
+    TileRef r;
+    bool dst_out;
+    if (!ph.tasks) {
+        r.in_k = b.in_k;
+        r.in_v = b.in_v;
+        dst_out = ph.dst_out != 0;
+        r.src_k = dst_out ? b.ws_k : b.out_k;
+        r.src_v = dst_out ? b.ws_v : b.out_v;
+        r.dst_k = dst_out ? b.out_k : b.ws_k;
+        r.dst_v = dst_out ? b.out_v : b.ws_v;
+        r.n = ph.n;
+        r.local = (uint32_t)t;
+        r.final_pass = ph.final_pass != 0;
+        return r;
+    }
+    const TileTask tk = ph.tasks[t];
+    const SegDesc& sd = ph.segs[tk.seg];
+    dst_out = (tk.info & kTaskDstOut) != 0;
+    r.in_k = sd.in_k;
+    r.in_v = sd.in_v;
+    r.src_k = dst_out ? sd.ws_k : sd.out_k;
+    r.src_v = dst_out ? sd.ws_v : sd.out_v;
+    r.dst_k = dst_out ? sd.out_k : sd.ws_k;
+    r.dst_v = dst_out ? sd.out_v : sd.ws_v;
+    r.n = sd.n;
+    r.local = tk.info & kTaskTileMask;
+    r.final_pass = (tk.info & kTaskFinal) != 0;
+    return r;
+}
 
 // Geometry of one merge round inside one segment: groups of K runs of length
 // L over n elements, each group cut into output tiles of Tout.

@@ -39,13 +39,13 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort(Phase ph, Bufs b, uint32_t
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const TileRef tr = tile_ref(ph, blockIdx.x);
-    const uint64_t base = tr.base + (uint64_t)tr.local * T;
-    const uint32_t cnt = (uint32_t)min<uint64_t>(T, tr.n - (uint64_t)tr.local * T);
-    const uint32_t* in_k = b.in_k + base;
-    const uint32_t* in_v = P ? b.in_v + base : nullptr;
-    uint32_t* out_k = (tr.dst_out ? b.out_k : b.ws_k) + base;
-    uint32_t* out_v = P ? (tr.dst_out ? b.out_v : b.ws_v) + base : nullptr;
+    const TileRef tr = tile_ref(ph, b, blockIdx.x);
+    const uint64_t base = (uint64_t)tr.local * T;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(T, tr.n - base);
+    const uint32_t* in_k = tr.in_k + base;
+    const uint32_t* in_v = P ? tr.in_v + base : nullptr;
+    uint32_t* out_k = tr.dst_k + base;
+    uint32_t* out_v = P ? tr.dst_v + base : nullptr;
     const uint32_t flip_out = tr.final_pass ? flip : 0u;
 
     Elem<P> r[E];
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort(Phase ph, Bufs b, uint32_t
         if constexpr (P) Xv[idx] = r[e].v;
     }
     if (threadIdx.x <= (unsigned)W) seg0[threadIdx.x] = threadIdx.x * CH;
-    __syncthreads();
+    lds_barrier();
 
     uint32_t* wscr = scr + (uint32_t)wave * Xpose<kEM1>::WORDS;
     const bool vec = ((uintptr_t)out_k & 15u) == 0;
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort(Phase ph, Bufs b, uint32_t
                 merge_level_keys<kEM1>(Xk, seg0, seg0, W, lvl, out, wscr, wave, W, lane);
             }
         }
-        __syncthreads();
+        lds_barrier();
         uint32_t* t = Xk; Xk = Yk; Yk = t;
         t = Xv; Xv = Yv; Yv = t;
     }
@@ -191,8 +191,7 @@ __global__ __launch_bounds__(256) void k_corank_tiles(Phase ph, Bufs b, RoundArg
     const int lane = threadIdx.x & 63;
     const uint64_t t = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (t >= ph.tiles) return;
-    const TileRef tr = tile_ref(ph, t);
-    const uint32_t* src = tr.dst_out ? b.ws_k : b.out_k;
+    const TileRef tr = tile_ref(ph, b, t);
     const uint32_t grp = tr.local / (uint32_t)ra.tpg;
     const uint64_t i = tr.local - (uint64_t)grp * ra.tpg;
     const uint64_t span = (uint64_t)ra.K * ra.L;
@@ -200,7 +199,7 @@ __global__ __launch_bounds__(256) void k_corank_tiles(Phase ph, Bufs b, RoundArg
     const uint64_t glen = min(span, tr.n - gb);
     const uint32_t Kg = (uint32_t)((glen + ra.L - 1) / ra.L);
     uint64_t c = 0;
-    if (i > 0) c = corank_wave(src, tr.base + gb, glen, ra.L, Kg, i * (uint64_t)ra.Tout, 0u, lane);
+    if (i > 0) c = corank_wave(tr.src_k, gb, glen, ra.L, Kg, i * (uint64_t)ra.Tout, 0u, lane);
     if ((uint32_t)lane < ra.K) table[t * ra.K + (uint64_t)lane] = (uint32_t)c;
 }
 
@@ -251,11 +250,11 @@ __global__ __launch_bounds__(W * 64) void k_merge_pairs(Phase ph, Bufs b, RoundA
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const uint64_t t = blockIdx.x;
-    const TileRef tr = tile_ref(ph, t);
-    const uint32_t* src_k = (tr.dst_out ? b.ws_k : b.out_k) + tr.base;
-    const uint32_t* src_v = (tr.dst_out ? b.ws_v : b.out_v) + tr.base;
-    uint32_t* dst_k = (tr.dst_out ? b.out_k : b.ws_k) + tr.base;
-    uint32_t* dst_v = (tr.dst_out ? b.out_v : b.ws_v) + tr.base;
+    const TileRef tr = tile_ref(ph, b, t);
+    const uint32_t* src_k = tr.src_k;
+    const uint32_t* src_v = tr.src_v;
+    uint32_t* dst_k = tr.dst_k;
+    uint32_t* dst_v = tr.dst_v;
     const uint32_t flip_out = tr.final_pass ? flip : 0u;
     const uint32_t grp = tr.local / (uint32_t)ra.tpg;
     const uint64_t i = tr.local - (uint64_t)grp * ra.tpg;
@@ -283,12 +282,12 @@ __global__ __launch_bounds__(W * 64) void k_merge_pairs(Phase ph, Bufs b, RoundA
         start[k] = s;
         seg0[k + 1] = e > s ? e - s : 0u;
     }
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) {
         seg0[0] = 0;
         for (uint32_t k = 0; k < Kg; ++k) seg0[k + 1] = min(seg0[k + 1] + seg0[k], cnt);
     }
-    __syncthreads();
+    lds_barrier();
     for (uint32_t k = 0; k < Kg; ++k) {
         const uint32_t dst0 = seg0[k], len = seg0[k + 1] - dst0;
         const uint64_t src0 = gb + (uint64_t)k * L + start[k];
@@ -297,7 +296,7 @@ __global__ __launch_bounds__(W * 64) void k_merge_pairs(Phase ph, Bufs b, RoundA
             Xv[dst0 + j] = src_v[src0 + j];
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     for (uint32_t lvl = 0; (1u << lvl) < Kg; ++lvl) {
         const bool last = (2u << lvl) >= Kg;
@@ -308,7 +307,7 @@ __global__ __launch_bounds__(W * 64) void k_merge_pairs(Phase ph, Bufs b, RoundA
             LdsSink<P> out{Yk, Yv};
             merge_level<kEM, P>(Xk, Xv, seg0, Kg, lvl, cnt, out, wave, W, lane);
         }
-        __syncthreads();
+        lds_barrier();
         uint32_t* tmp = Xk; Xk = Yk; Yk = tmp;
         tmp = Xv; Xv = Yv; Yv = tmp;
     }

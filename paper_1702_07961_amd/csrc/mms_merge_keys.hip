@@ -22,33 +22,35 @@ namespace mms {
 namespace {
 
 struct TileGeo {
-    uint64_t gb;      // group start (absolute position)
+    const uint32_t* src;  // buffer the round reads (segment start)
+    uint32_t* dst;        // buffer the round writes (segment start)
+    uint64_t gb;      // group start inside the segment
     uint64_t glen;    // group size
     uint64_t obeg;    // tile start inside the group
     uint32_t Kg;      // runs in the group
     uint32_t cnt;     // outputs of the tile
     bool first;       // first tile of its group
     bool last;        // last tile of its group
-    bool dst_out;     // the pass writes the output buffer
     bool final_pass;  // last pass of the segment
 };
 
-__device__ __forceinline__ TileGeo tile_geo(const Phase& ph, uint64_t t, const RoundArgs& ra) {
-    const TileRef tr = tile_ref(ph, t);
+__device__ __forceinline__ TileGeo tile_geo(const Phase& ph, const Bufs& b, uint64_t t, const RoundArgs& ra) {
+    const TileRef tr = tile_ref(ph, b, t);
     TileGeo g;
     // tile counts stay far below 2^32, so 32-bit division suffices
     const uint32_t grp = tr.local / (uint32_t)ra.tpg;
     const uint64_t i = tr.local - (uint64_t)grp * ra.tpg;
     const uint64_t span = (uint64_t)ra.K * ra.L;
     const uint64_t gb = (uint64_t)grp * span;
-    g.gb = tr.base + gb;
+    g.src = tr.src_k;
+    g.dst = tr.dst_k;
+    g.gb = gb;
     g.glen = min(span, tr.n - gb);
     g.Kg = (uint32_t)((g.glen + ra.L - 1) / ra.L);
     g.obeg = i * (uint64_t)ra.Tout;
     g.cnt = (uint32_t)min<uint64_t>(ra.Tout, g.glen - g.obeg);
     g.first = i == 0;
     g.last = g.obeg + ra.Tout >= g.glen;
-    g.dst_out = tr.dst_out;
     g.final_pass = tr.final_pass;
     return g;
 }
@@ -145,7 +147,6 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
     const uint32_t tid = threadIdx.x;
     const uint64_t G = gridDim.x;
     uint32_t* wscr = scr + (uint32_t)wave * Xpose<EM>::WORDS;
-    const bool vec_base = (((uintptr_t)b.out_k | (uintptr_t)b.ws_k) & 15u) == 0;
 
     uint64_t t = blockIdx.x;
     if (t >= tiles) return;
@@ -156,8 +157,8 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
     uint32_t nx_s = 0, nx_e = 0;   // wave 0: split indices of the tile after next
 
     auto issue_loads = [&](uint64_t tt, const Meta& m) {
-        const TileGeo g = tile_geo(ph, tt, ra);
-        const uint32_t* src = g.dst_out ? b.ws_k : b.out_k;
+        const TileGeo g = tile_geo(ph, b, tt, ra);
+        const uint32_t* src = g.src;
 #pragma unroll
         for (int r = 0; r < PF; ++r) {
             const uint32_t j = (uint32_t)r * NT + tid;
@@ -179,23 +180,23 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
 
     // prologue: piece table and keys of the first tile, split of the second
     {
-        const TileGeo g0 = tile_geo(ph, t, ra);
+        const TileGeo g0 = tile_geo(ph, b, t, ra);
         if (wave == 0) {
             uint32_t s, e;
             load_split(table, t, g0, L, K, lane, s, e);
             build_meta(meta(0), s, e, g0, lane);
-            if (t + G < tiles) load_split(table, t + G, tile_geo(ph, t + G, ra), L, K, lane, nx_s, nx_e);
+            if (t + G < tiles) load_split(table, t + G, tile_geo(ph, b, t + G, ra), L, K, lane, nx_s, nx_e);
         }
-        __syncthreads();
+        lds_barrier();
         issue_loads(t, meta(0));
         store_loads(bufA);
-        __syncthreads();
+        lds_barrier();
     }
 
     int cur = 0;
     for (;;) {
-        const TileGeo g = tile_geo(ph, t, ra);
-        uint32_t* dst = g.dst_out ? b.out_k : b.ws_k;
+        const TileGeo g = tile_geo(ph, b, t, ra);
+        uint32_t* dst = g.dst;
         const uint32_t flip_out = g.final_pass ? flip : 0u;
         const Meta mc = meta(cur);
         const Meta mn = meta(cur ^ 1);
@@ -204,10 +205,10 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
 
         // wave 0: piece table of the next tile, split indices of the one after
         if (wave == 0 && has_next) {
-            const TileGeo gn = tile_geo(ph, tn, ra);
+            const TileGeo gn = tile_geo(ph, b, tn, ra);
             build_meta(mn, nx_s, nx_e, gn, lane);
             if (tn + G < tiles)
-                load_split(table, tn + G, tile_geo(ph, tn + G, ra), L, K, lane, nx_s, nx_e);
+                load_split(table, tn + G, tile_geo(ph, b, tn + G, ra), L, K, lane, nx_s, nx_e);
         }
 
         uint32_t* X = bufA;
@@ -215,14 +216,14 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
         const uint64_t obase = g.gb + g.obeg;
         bool issued = false;
         if (g.Kg == 1) {
-            __syncthreads();
+            lds_barrier();
             if (has_next) {
                 issue_loads(tn, mn);
                 issued = true;
             }
             for (uint32_t j = tid; j < g.cnt; j += NT) dst[obase + j] = X[j] ^ flip_out;
         } else {
-            const bool vec = vec_base && (obase & 3u) == 0;
+            const bool vec = ((uintptr_t)(dst + obase) & 15u) == 0;
             for (uint32_t lvl = 0; (1u << lvl) < g.Kg; ++lvl) {
                 const bool last = (2u << lvl) >= g.Kg;
                 if (last) {
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
                     LdsSinkKeys out{Y};
                     merge_level_keys<EM>(X, mc.sbeg, mc.plen, g.Kg, lvl, out, wscr, wave, W, lane);
                 }
-                __syncthreads();
+                lds_barrier();
                 // the next tile's piece table is visible now; its loads overlap
                 // the remaining levels
                 if (!issued && has_next) {
@@ -243,9 +244,9 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
             }
         }
         if (!has_next) break;
-        __syncthreads();        // every wave is done reading this tile's LDS
+        lds_barrier();        // every wave is done reading this tile's LDS
         store_loads(bufA);
-        __syncthreads();
+        lds_barrier();
         t = tn;
         cur ^= 1;
     }
