@@ -64,15 +64,15 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(x_host):
+def cpu_baseline(x_host, i32: bool = False):
     import oracle
     sample = 1 << 25
     xs = x_host[:sample].copy()
     t0 = time.perf_counter()
-    oracle.sort(xs)
+    oracle.sort(xs, i32=i32)
     dt = time.perf_counter() - t0
     return {"value": round(sample / dt / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-            "sample": f"first 2^25 keys of the same uniform uint32 input, sequential heap-based "
+            "sample": f"first 2^25 keys of the same input, sequential heap-based "
                       f"5-way mergesort, {dt:.2f} s"}
 
 
@@ -236,12 +236,24 @@ def bench_serving(mms, torch, np, mmsgen, count: int = 2100, warm: int = 100, rh
             "p99_per_call_over_served": round(per_call["p99_ms"] / served["p99_ms"], 3)}
 
 
+def make_input(mmsgen, np, family: str, n: int, swaps: int):
+    seed = mmsgen.seed_for(2, 0)
+    if family == "nearly":
+        return mmsgen.nearly_sorted_u32(seed, n, swaps)
+    return mmsgen.family(family, seed, n)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_KEYS)
+    ap.add_argument("--family", default="uniform",
+                    choices=["uniform", "nearly", "sixteen", "stride64", "permutation", "sorted", "reverse"])
+    ap.add_argument("--swaps", type=int, default=0, help="random pair swaps of the nearly-sorted family")
+    ap.add_argument("--i32", action="store_true", help="int32 keys (signed order)")
+    ap.add_argument("--pairs", action="store_true", help="stable (key, index) pairs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-sort comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop comparison")
@@ -258,15 +270,24 @@ def main():
     import paper_1702_07961_amd as mms
 
     n = args.n
-    x_host = mmsgen.uniform_u32(mmsgen.seed_for(2, 0), n)
+    headline = (args.family == "uniform" and not args.i32 and not args.pairs and n == N_KEYS)
+    x_host = make_input(mmsgen, np, args.family, n, args.swaps)
     x = torch.from_numpy(x_host.view(np.int32)).cuda()
     out = torch.empty_like(x)
-    ws = torch.empty(max(1, mms.workspace_bytes(n)), dtype=torch.uint8, device="cuda")
+    v = torch.arange(n, dtype=torch.int32, device="cuda") if args.pairs else None
+    vout = torch.empty_like(v) if args.pairs else None
+    ws = torch.empty(max(1, mms.workspace_bytes(n, pairs=args.pairs)), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
-    plan = mms.plan(n)
+    plan = mms.plan(n, pairs=args.pairs, i32=args.i32)
+
+    def step():
+        if args.pairs:
+            mms.sort_pairs(x, v, out_keys=out, out_values=vout, i32=args.i32, workspace=ws)
+        else:
+            mms.sort(x, out=out, i32=args.i32, workspace=ws)
 
     for _ in range(args.warmup):
-        mms.sort(x, out=out, i32=False, workspace=ws)
+        step()
     torch.cuda.synchronize()
 
     mms.timing_reset()
@@ -276,23 +297,30 @@ def main():
     torch.cuda.synchronize()
     start.record(stream)
     for _ in range(args.steps):
-        mms.sort(x, out=out, i32=False, workspace=ws)
+        step()
     stop.record(stream)
     torch.cuda.synchronize()
     mms.timing_enable(False)
     times = mms.timing_read()
     ms_per_step = start.elapsed_time(stop) / args.steps
 
-    # the result of the timed steps must be sorted (cheap device check)
-    o = out.to(torch.int64) & 0xFFFFFFFF
-    if not bool((o[1:] >= o[:-1]).all()):
+    # the result of the timed steps must be sorted, and stable for pairs (device check)
+    o = out.to(torch.int64)
+    if not args.i32:
+        o = o & 0xFFFFFFFF
+    ok = bool((o[1:] >= o[:-1]).all())
+    if args.pairs:
+        tie = o[1:] == o[:-1]
+        ok = ok and bool((vout[1:][tie] > vout[:-1][tie]).all())
+    if not ok:
         print("bench.py: output is not sorted", file=sys.stderr)
         sys.exit(1)
 
+    s_bytes = 8 if args.pairs else 4
     gkeys = n / (ms_per_step * 1e-3) / 1e9
     m_launches, m_ms = times["merge"]
     merge_avg_ms = m_ms / max(1, m_launches)
-    alg_bytes = 2 * 4 * n   # one read and one write of every key per merge launch
+    alg_bytes = 2 * s_bytes * n   # one read and one write of every element per merge launch
     achieved = alg_bytes / (merge_avg_ms * 1e-3) / 1e9
     phases = {k: {"launches": c, "ms_per_step": round(t / args.steps, 4)} for k, (c, t) in times.items()
               if c}
@@ -308,6 +336,11 @@ def main():
     c_launch, c_ms = mms.timing_read()["copy"]
     copy_gbs = 2 * 4 * n / (c_ms / c_launch * 1e-3) / 1e9
 
+    fam = args.family + (f" ({args.swaps} swaps)" if args.family == "nearly" else "")
+    workload = (f"plain {'stable pair' if args.pairs else 'keys-only'} sort of {n} {fam} "
+                f"{'int32' if args.i32 else 'uint32'} keys, ascending")
+    if headline:
+        workload = "plain sort of 1e8 uniform uint32 keys, keys only, ascending"
     rec = {
         "metric": METRIC,
         "value": round(gkeys, 4),
@@ -319,27 +352,27 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": ("i32" if args.i32 else "u32") + ("+u32 pairs" if args.pairs else ""),
         "data": "synthetic",
-        "config": {"workload": "plain sort of 1e8 uniform uint32 keys, keys only, ascending",
-                   "n": n, "input": "splitmix64 >> 32, seed 0x4D4D5320",
+        "config": {"workload": workload,
+                   "n": n, "input": f"{fam}, splitmix64 seed 0x4D4D5320",
                    "base_tile": plan.tile, "fanout": plan.fanout, "merge_tile": plan.merge_tile,
                    "passes": plan.passes},
         "roofline": {"bound": "hbm", "kernel": "k_merge", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(),
+                     "traffic": measured_traffic() if headline else None,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": round(merge_avg_ms, 4)},
         "detail": {"phases": phases,
                    "all_passes_alg_GBps": round(plan.passes * alg_bytes / (ms_per_step * 1e-3) / 1e9, 1),
                    "copy_probe_GBps": round(copy_gbs, 1)},
     }
-    if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(x_host)
-    del x, out, ws
-    if not args.no_batched:
+    if not args.no_cpu and not args.pairs:
+        rec["cpu_baseline"] = cpu_baseline(x_host, args.i32)
+    del x, out, ws, v, vout
+    if headline and not args.no_batched:
         rec["batched"] = bench_batched(mms, torch, np, mmsgen)
-    if not args.no_serving:
+    if headline and not args.no_serving:
         rec["serving"] = bench_serving(mms, torch, np, mmsgen)
     print(json.dumps(rec), flush=True)
 

@@ -7,10 +7,14 @@ library must be built (``paper_1702_07961_amd.build``); there is no fallback.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmms.so")
+# tuning table written by paper_1702_07961_amd.autotune; MMS_TUNING_FILE
+# overrides the path, an empty value keeps the library's built-in default
+TUNING_PATH = os.path.join(PKG, "tuning_mi355x.json")
 
 MMS_OK = 0
 MMS_PENDING = 1
@@ -186,7 +190,24 @@ def lib() -> ctypes.CDLL:
                 f"{LIB_PATH} is missing: build it with `python -m paper_1702_07961_amd.build` "
                 "(the HIP library is required; there is no CPU fallback)")
         _lib = _declare(ctypes.CDLL(LIB_PATH))
+        load_tuning(_lib)
     return _lib
+
+
+def load_tuning(lib, path: str | None = None) -> int:
+    """Install the autotuned table (if present); returns the entry count."""
+    if path is None:
+        path = os.environ.get("MMS_TUNING_FILE", TUNING_PATH)
+    if not path or not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        entries = json.load(f)["entries"]
+    arr = (MmsTuning * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        arr[i] = MmsTuning(int(e["max_log2_n"]), int(e["fanout"]), int(e["merge_tile"]), int(e["variant"]))
+    if lib.mms_set_tuning(arr, len(entries)) != MMS_OK:
+        raise MmsError(MMS_EINVAL, f"{path}: " + lib.mms_last_error().decode())
+    return len(entries)
 
 
 def check(code: int) -> int:

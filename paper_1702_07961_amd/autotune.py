@@ -1,0 +1,110 @@
+"""Autotuner of the sort's run-time parameters (§6.2 tunes the fan-out K and
+the number of workers per platform; here per size bucket on this GPU).
+
+For every size bucket n = 2^b it times the plain keys-only sort of n uniform
+uint32 keys under each candidate (fan-out K, merge output tile, merge kernel
+shape) with HIP events, keeps the fastest, and writes the table as JSON.
+The package loads that table into the library (mms_set_tuning) the first
+time the library is used.
+
+    python -m paper_1702_07961_amd.autotune [--out FILE] [--min-log2 8]
+                                            [--max-log2 27] [--reps 5]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_TABLE = os.path.join(PKG, "tuning_mi355x.json")
+
+FANOUTS = [4, 8, 16]
+TILES = [2048, 4096, 8192]
+VARIANTS = [0, 1, 2]
+
+
+def candidates(log2n: int):
+    """Every (K, Tout, variant) to time for n = 2^log2n (a single tile has
+    no merge round, so nothing to choose)."""
+    if (1 << log2n) <= 2048:
+        yield 16, 8192, 0
+        return
+    for K in FANOUTS:
+        for T in TILES:
+            for v in VARIANTS:
+                yield K, T, v
+
+
+def time_sort(mms, torch, x, out, ws, reps: int) -> float:
+    stream = torch.cuda.current_stream()
+    mms.sort(x, out=out, i32=False, workspace=ws)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        mms.sort(x, out=out, i32=False, workspace=ws)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune(min_log2: int = 8, max_log2: int = 27, reps: int = 5, log=print) -> dict:
+    import numpy as np
+    import torch
+
+    import mmsgen
+    import paper_1702_07961_amd as mms
+
+    n_max = 1 << max_log2
+    x_all = torch.from_numpy(mmsgen.uniform_u32(mmsgen.seed_for(6, 0), n_max).view(np.int32)).cuda()
+    out_all = torch.empty_like(x_all)
+    entries = []
+    for b in range(min_log2, max_log2 + 1):
+        n = 1 << b
+        x, out = x_all[:n], out_all[:n]
+        best = None
+        for K, T, v in candidates(b):
+            mms.set_tuning([(64, K, T, v)])
+            ws_bytes = mms.workspace_bytes(n)
+            ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device="cuda")
+            r = max(reps, int(2e6 // n))
+            ms = time_sort(mms, torch, x, out, ws, r)
+            if best is None or ms < best[0]:
+                best = (ms, K, T, v)
+        ms, K, T, v = best
+        # the fastest candidate must still sort
+        mms.set_tuning([(64, K, T, v)])
+        ws = torch.empty(max(mms.workspace_bytes(n), 256), dtype=torch.uint8, device="cuda")
+        mms.sort(x, out=out, i32=False, workspace=ws)
+        o = out.to(torch.int64) & 0xFFFFFFFF
+        if not bool((o[1:] >= o[:-1]).all()):
+            raise RuntimeError(f"tuned sort of 2^{b} is not sorted")
+        entries.append({"max_log2_n": b, "fanout": K, "merge_tile": T, "variant": v,
+                        "ms": round(ms, 5), "gkeys_per_s": round(n / ms / 1e6, 3)})
+        log(f"2^{b}: K={K} Tout={T} variant={v} {ms:.4f} ms ({n / ms / 1e6:.2f} Gkeys/s)")
+    mms.set_tuning([])
+    props = torch.cuda.get_device_properties(0)
+    return {"device": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
+            "cus": props.multi_processor_count, "created": time.strftime("%Y-%m-%d %H:%M:%S"),
+            "method": "plain keys-only sort of 2^b uniform uint32 keys, HIP-event mean over reps",
+            "entries": entries}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_TABLE)
+    ap.add_argument("--min-log2", type=int, default=8)
+    ap.add_argument("--max-log2", type=int, default=27)
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args(argv)
+    table = tune(args.min_log2, args.max_log2, args.reps, log=lambda s: print(s, flush=True))
+    with open(args.out, "w") as f:
+        json.dump(table, f, indent=1)
+    print(f"wrote {args.out}", file=sys.stderr)
+
+
+if __name__ == "__main__":
+    main()

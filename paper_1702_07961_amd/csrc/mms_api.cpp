@@ -205,17 +205,40 @@ void build_batch_tasks(const uint64_t* seg_n, uint64_t ns, bool pairs, const Tun
     }
 }
 
-// With T = 2048, K >= 2 and Tout >= 1024: a segment of n elements has at
-// most n/2048 + 1 base tiles and, per round, at most n/1024 tiles plus one
-// per group (n/4096 + 1 groups); it has at most rounds_for(n, 2048, 2) rounds.
-static uint64_t round_tiles_bound(uint64_t total, uint64_t ns) { return (5 * total) / 4096 + 2 * ns + 1; }
-
-uint64_t batch_tasks_bound(uint64_t total, uint64_t ns) {
-    return total / kT1 + ns + 1 + (uint64_t)rounds_for(total, kT1, 2) * round_tiles_bound(total, ns);
+// A segment of n elements has at most n/T + 1 base tiles; round r has at
+// most n/Tout + n/(T*K) + 1 tiles (one per Tout outputs plus one per group,
+// groups <= n/(K*L) + 1 with L >= T); it has at most rounds_for(n, T, K)
+// rounds.
+uint64_t batch_tasks_bound(uint64_t total, uint64_t ns, uint64_t maxn, uint32_t K, uint32_t Tout) {
+    const uint64_t round = total / Tout + total / ((uint64_t)kT1 * K) + ns + 1;
+    return total / kT1 + ns + 1 + (uint64_t)rounds_for(maxn, kT1, K) * round;
 }
 
-uint64_t batch_table_bound(uint64_t total, uint64_t ns) {
-    return align_up((round_tiles_bound(total, ns) + 1) * kMaxFanout * 4);
+uint64_t batch_table_bound(uint64_t total, uint64_t ns, uint32_t Tout) {
+    // groups are at least 2T long, so per-round tiles <= total/Tout + total/(2T) + ns + 1
+    const uint64_t round = total / Tout + total / (2ull * kT1) + ns + 1;
+    return align_up((round + 1) * kMaxFanout * 4);
+}
+
+void tuning_floor(uint32_t& K, uint32_t& Tout) {
+    const Tune d = tune_for(1ull << 20, false);
+    K = d.K;
+    Tout = std::min<uint32_t>(d.Tout, kToutPairs);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (const auto& x : g_tuning) {
+        if (!valid_tune(x.fanout, x.merge_tile, (int)x.variant)) continue;
+        K = std::min(K, x.fanout);
+        Tout = std::min(Tout, x.merge_tile);
+    }
+}
+
+void add_segment_tiles(uint64_t n, const Tune& tune, std::vector<uint64_t>& per_phase) {
+    if (n == 0) return;
+    const uint32_t R = rounds_for(n, kT1, tune.K);
+    if (per_phase.size() < (size_t)R + 1) per_phase.resize(R + 1, 0);
+    per_phase[0] += (n + kT1 - 1) / kT1;
+    uint64_t L = kT1;
+    for (uint32_t r = 0; r < R; ++r, L *= tune.K) per_phase[1 + r] += round_geom(n, L, tune.K, tune.Tout).tiles;
 }
 
 int run_batch(const BatchTasks& bt, const SegDesc* d_segs, const TileTask* d_tasks, uint32_t* table, uint32_t flip,

@@ -158,23 +158,27 @@ template <> __device__ __forceinline__ Elem<true> lds_get<true>(const uint32_t* 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t lds_corank2(const uint32_t* Xk, uint32_t aA, uint32_t la, uint32_t aB,
                                                 uint32_t lb, uint32_t d, int lane) {
-    uint32_t lo = d > lb ? d - lb : 0u;
-    uint32_t hi = min(d, la);
+    // wave-uniform bounds, kept in scalar registers
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(d > lb ? d - lb : 0u));
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)min(d, la));
     while (lo < hi) {
-        // 128 probes per round: probe q = lane + 64*j sits at lo + q*step
+        // 128 probes per round: probe q = lane + 64*j sits at lo + q*step.
+        // A probe past hi reads the last valid position instead (every
+        // index stays inside both runs) and does not count.
         const uint32_t R = hi - lo;
         const uint32_t step = ((R + 127u) >> 7) | 1u;
         const uint32_t m0 = lo + (uint32_t)lane * step;
         const uint32_t m1 = m0 + 64u * step;
-        bool p0 = false, p1 = false;
-        if (m0 < hi) p0 = Xk[aA + m0] <= Xk[aB + d - 1u - m0];
-        if (m1 < hi) p1 = Xk[aA + m1] <= Xk[aB + d - 1u - m1];
+        const bool v0 = m0 < hi, v1 = m1 < hi;
+        const uint32_t c0 = v0 ? m0 : hi - 1u, c1 = v1 ? m1 : hi - 1u;
+        const bool p0 = v0 && Xk[aA + c0] <= Xk[aB + d - 1u - c0];
+        const bool p1 = v1 && Xk[aA + c1] <= Xk[aB + d - 1u - c1];
         const uint32_t t = (uint32_t)__popcll(__ballot(p0)) + (uint32_t)__popcll(__ballot(p1));
-        const uint32_t nvalid = min(128u, (R + step - 1u) / step);
+        const uint32_t nvalid = (uint32_t)__popcll(__ballot(v0)) + (uint32_t)__popcll(__ballot(v1));
         const uint32_t nlo = t > 0 ? lo + (t - 1u) * step + 1u : lo;
         const uint32_t nhi = t < nvalid ? lo + t * step : hi;
-        lo = nlo;
-        hi = nhi;
+        lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)nlo);
+        hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)nhi);
     }
     return lo;
 }
@@ -421,35 +425,48 @@ __device__ __forceinline__ void merge_pair_range_keys(const uint32_t* X, uint32_
     constexpr uint32_t N = (uint32_t)kWave * EM;
     uint32_t p = lds_corank2(X, aA, la, aB, lb, d0, lane);
     uint32_t q = d0 - p;
+    // last readable index of each run (any LDS word is readable when empty)
+    const uint32_t la1 = la ? la - 1u : 0u, lb1 = lb ? lb - 1u : 0u;
     for (uint32_t o = d0; o < d1; o += N) {
         uint32_t m[EM];
         uint32_t u = 0;
         if (p + N <= la && q + N <= lb) {
             const uint32_t* Ap = X + aA + p + (uint32_t)lane;
             const uint32_t* Bp = X + aB + q + (N - 1u) - (uint32_t)lane;
+            uint32_t a[EM], b[EM];
+#pragma unroll
+            for (int e = 0; e < EM; ++e) {      // all reads in flight together
+                a[e] = Ap[e * kWave];
+                b[e] = Bp[-(e * kWave)];
+            }
 #pragma unroll
             for (int e = 0; e < EM; ++e) {
-                const uint32_t a = Ap[e * kWave];
-                const uint32_t b = Bp[-(e * kWave)];
-                m[e] = min(a, b);
-                u += (uint32_t)__popcll(__ballot(a <= b));
+                m[e] = min(a[e], b[e]);
+                u += (uint32_t)__popcll(__ballot(a[e] <= b[e]));
             }
         } else {
+            // near the end of a run: read a clamped index and substitute the
+            // sentinel, with no branch per element
+            uint32_t a[EM], b[EM];
 #pragma unroll
             for (int e = 0; e < EM; ++e) {
                 const uint32_t k = (uint32_t)e * kWave + (uint32_t)lane;
-                const uint32_t ia = p + k;
-                const uint32_t jb = q + (N - 1u - k);
-                const uint32_t a = ia < la ? X[aA + ia] : kSentKey;
-                const uint32_t b = jb < lb ? X[aB + jb] : kSentKey;
-                m[e] = min(a, b);
-                u += (uint32_t)__popcll(__ballot(a <= b));
+                a[e] = X[aA + min(p + k, la1)];
+                b[e] = X[aB + min(q + (N - 1u - k), lb1)];
+            }
+#pragma unroll
+            for (int e = 0; e < EM; ++e) {
+                const uint32_t k = (uint32_t)e * kWave + (uint32_t)lane;
+                const uint32_t av = p + k < la ? a[e] : kSentKey;
+                const uint32_t bv = q + (N - 1u - k) < lb ? b[e] : kSentKey;
+                m[e] = min(av, bv);
+                u += (uint32_t)__popcll(__ballot(av <= bv));
             }
         }
         block_sort_keys<EM>(m, scr, lane);
         out.template put_block<EM>(out_base + o, min(N, d1 - o), m, lane);
-        p += u;
-        q += N - u;
+        p = (uint32_t)__builtin_amdgcn_readfirstlane((int)(p + u));
+        q = (uint32_t)__builtin_amdgcn_readfirstlane((int)(q + N - u));
     }
 }
 

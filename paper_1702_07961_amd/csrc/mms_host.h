@@ -75,10 +75,19 @@ struct BatchTasks {
 };
 void build_batch_tasks(const uint64_t* seg_n, uint64_t ns, bool pairs, const Tune& tune, BatchTasks& bt);
 
-// Upper bound on the task count and partition-table bytes of any batch of
-// at most `ns` segments and `total` elements, over every valid tuning.
-uint64_t batch_tasks_bound(uint64_t total, uint64_t ns);
-uint64_t batch_table_bound(uint64_t total, uint64_t ns);
+// Smallest fan-out and merge tile any sort can currently be planned with
+// (over the tuning table, the default, and the key-value tile).
+void tuning_floor(uint32_t& K, uint32_t& Tout);
+
+// Upper bounds on the task count and partition-table bytes of a batch of at
+// most `ns` segments, `total` elements and segments of at most `maxn`
+// elements, planned with fan-out >= K and merge tile >= Tout.
+uint64_t batch_tasks_bound(uint64_t total, uint64_t ns, uint64_t maxn, uint32_t K, uint32_t Tout);
+uint64_t batch_table_bound(uint64_t total, uint64_t ns, uint32_t Tout);
+
+// Tiles of each phase of the plain sort of n elements under `tune`
+// (entry 0: base case, entry 1 + r: round r), added to `per_phase`.
+void add_segment_tiles(uint64_t n, const Tune& tune, std::vector<uint64_t>& per_phase);
 
 // Enqueue every phase of a batch on stream s.  d_segs holds its SegDesc
 // table and d_tasks its task lists phase after phase (device memory);

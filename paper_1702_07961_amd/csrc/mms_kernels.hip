@@ -38,7 +38,7 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort(Phase ph, Bufs b, uint32_t
     uint32_t* scr = seg0 + 32;                       // keys: W wave-private transpose scratches
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
     const TileRef tr = tile_ref(ph, b, blockIdx.x);
     const uint64_t base = (uint64_t)tr.local * T;
     const uint32_t cnt = (uint32_t)min<uint64_t>(T, tr.n - base);
@@ -150,10 +150,15 @@ __device__ uint64_t corank_wave(const uint32_t* __restrict__ keys, uint64_t gb, 
         const uint32_t off = incl - cnt;
         const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 15);
 
-        // candidate owned by this lane: run kk, block j
+        // candidate owned by this lane: run kk = the last k with off_k <= lane
+        // (off is non-decreasing, so that is the number of k >= 1 with
+        // off_k <= lane); straight-line, with off_k read into scalars
         uint32_t kk = 0;
-        for (uint32_t k = 1; k < Kg; ++k)
-            if ((uint32_t)__builtin_amdgcn_readlane((int)off, (int)k) <= (uint32_t)lane) kk = k;
+#pragma unroll
+        for (uint32_t k = 1; k < kMaxFanout; ++k) {
+            const uint32_t ok = (uint32_t)__builtin_amdgcn_readlane((int)off, (int)k);
+            kk += (k < Kg && ok <= (uint32_t)lane) ? 1u : 0u;
+        }
         const bool valid = (uint32_t)lane < total;
         const uint32_t my_off = (uint32_t)__shfl((int)off, (int)kk, 64);
         const uint32_t my_jlo = (uint32_t)__shfl((int)jlo, (int)kk, 64);
@@ -172,8 +177,10 @@ __device__ uint64_t corank_wave(const uint32_t* __restrict__ keys, uint64_t gb, 
         const int64_t num = (int64_t)r - (int64_t)Kg * (int64_t)hm1;
         const uint64_t tlo = num > 0 ? ((uint64_t)num + hm1) >> l : 0;
         const uint64_t thi = r >> l;
-        const uint32_t mlo = tlo > sum2lo ? (uint32_t)min<uint64_t>(tlo - sum2lo, total) : 0u;
-        const uint32_t mhi = thi > sum2lo ? (uint32_t)min<uint64_t>(thi - sum2lo, total) : 0u;
+        const uint64_t dlo = tlo > sum2lo ? tlo - sum2lo : 0u;
+        const uint64_t dhi = thi > sum2lo ? thi - sum2lo : 0u;
+        const uint32_t mlo = dlo < (uint64_t)total ? (uint32_t)dlo : total;
+        const uint32_t mhi = dhi < (uint64_t)total ? (uint32_t)dhi : total;
         const uint64_t blo = __ballot(valid && rank < mlo);
         const uint64_t bhi = __ballot(valid && rank < mhi);
         const uint64_t mask = cnt ? (((cnt >= 64 ? ~0ull : ((1ull << cnt) - 1))) << off) : 0ull;
@@ -248,7 +255,7 @@ __global__ __launch_bounds__(W * 64) void k_merge_pairs(Phase ph, Bufs b, RoundA
     uint32_t* start = seg0 + kMaxFanout + 1;      // [kMaxFanout]
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
     const uint64_t t = blockIdx.x;
     const TileRef tr = tile_ref(ph, b, t);
     const uint32_t* src_k = tr.src_k;

@@ -143,7 +143,7 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
     };
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
     const uint32_t tid = threadIdx.x;
     const uint64_t G = gridDim.x;
     uint32_t* wscr = scr + (uint32_t)wave * Xpose<EM>::WORDS;

@@ -111,6 +111,7 @@ struct Req {
 
 struct Batch {
     uint64_t id = 0;
+    Tune tune{};
     std::vector<uint64_t> tickets;
     int slot = -1;
     int stream = 0;
@@ -261,20 +262,66 @@ int pick_stream(mms_server* s) {
     return best;
 }
 
+// Device bytes of a batch's metadata: SegDesc table, task lists, partition
+// table.
+uint64_t meta_bytes(uint64_t segs, uint64_t ntasks, uint64_t max_round_tiles, uint32_t K, bool rounds) {
+    return align_up(align_up(segs * sizeof(mms::SegDesc)) + ntasks * sizeof(mms::TileTask)) +
+           (rounds ? align_up((max_round_tiles + 1) * K * 4) : 0);
+}
+
 // The next batch: the oldest admitted request and, in admission order, every
-// later one of the same kind within the batch limits.
+// later one of the same kind within the batch limits and the metadata slot.
+// The batch is planned with the tuning of its largest candidate.
 Batch form_batch(mms_server* s, int stream, int slot) {
     Batch b;
     b.id = s->next_batch++;
     b.stream = stream;
     b.slot = slot;
     const uint32_t kind = s->reqs[s->admitted.front()].r.flags;
-    uint64_t keys = 0;
+    uint64_t maxn = 0;
+    for (uint64_t t : s->admitted) {
+        const Req& q = s->reqs[t];
+        if (q.r.flags == kind) maxn = std::max(maxn, q.r.n);
+    }
+    b.tune = tune_for(maxn, (kind & MMS_PAIRS) != 0);
+    uint64_t keys = 0, ntasks = 0;
+    std::vector<uint64_t> phases, mine;
     std::deque<uint64_t> rest;
     for (uint64_t t : s->admitted) {
         Req& q = s->reqs[t];
-        const bool fits = b.tickets.size() < s->cfg.max_batch_requests && keys + q.r.n <= s->cfg.max_batch_keys;
-        if (q.r.flags == kind && fits) {
+        bool take = q.r.flags == kind && b.tickets.size() < s->cfg.max_batch_requests &&
+                    keys + q.r.n <= s->cfg.max_batch_keys;
+        if (take) {
+            mine.assign(phases.size(), 0);
+            add_segment_tiles(q.r.n, b.tune, mine);
+            std::vector<uint64_t> sum(std::max(phases.size(), mine.size()), 0);
+            uint64_t add = 0, maxr = 0;
+            for (size_t p = 0; p < sum.size(); ++p) {
+                const uint64_t a = p < phases.size() ? phases[p] : 0, m = p < mine.size() ? mine[p] : 0;
+                sum[p] = a + m;
+                add += m;
+                if (p) maxr = std::max(maxr, sum[p]);
+            }
+            if (meta_bytes(b.tickets.size() + 1, ntasks + add, maxr, b.tune.K, sum.size() > 1) <= s->slot_bytes) {
+                phases.swap(sum);
+                ntasks += add;
+            } else {
+                take = false;
+                if (b.tickets.empty() && t == s->admitted.front()) {
+                    // cannot run even alone (the tuning changed after creation)
+                    s->alloc.release(q.ws_off, q.ws_bytes);
+                    q.ws_bytes = 0;
+                    q.st = St::Failed;
+                    q.status = MMS_EINVAL;
+                    q.err = "request needs more batch metadata than a slot holds under the current tuning";
+                    q.t_done = s->now_us();
+                    ++s->stats.completed;
+                    s->cv_done.notify_all();
+                    continue;
+                }
+            }
+        }
+        if (take) {
             b.tickets.push_back(t);
             keys += q.r.n;
         } else {
@@ -320,16 +367,12 @@ void enqueue_batch(mms_server* s, Batch& b, std::vector<Req*>& rq) {
     }
     if (b.status == MMS_OK) {
         std::vector<uint64_t> seg_n(rq.size());
-        uint64_t maxn = 0;
-        for (size_t i = 0; i < rq.size(); ++i) {
-            seg_n[i] = rq[i]->r.n;
-            maxn = std::max(maxn, seg_n[i]);
-        }
+        for (size_t i = 0; i < rq.size(); ++i) seg_n[i] = rq[i]->r.n;
         BatchTasks bt;
-        build_batch_tasks(seg_n.data(), seg_n.size(), pairs, tune_for(maxn, pairs), bt);
+        build_batch_tasks(seg_n.data(), seg_n.size(), pairs, b.tune, bt);
         const uint64_t seg_bytes = align_up(rq.size() * sizeof(mms::SegDesc));
         const uint64_t img_bytes = align_up(seg_bytes + bt.ntasks * sizeof(mms::TileTask));
-        if (img_bytes + bt.table_bytes() > s->slot_bytes) {
+        if (img_bytes + bt.table_bytes() > s->slot_bytes) {   // excluded when the batch was formed
             b.status = MMS_EINVAL;
             b.err = "batch metadata exceeds its slot";
         } else {
@@ -430,6 +473,11 @@ void scheduler_main(mms_server* s) {
             const int slot = s->free_slots.back();
             s->free_slots.pop_back();
             Batch b = form_batch(s, stream, slot);
+            if (b.tickets.empty()) {
+                s->free_slots.push_back(slot);
+                --s->stats.batches;
+                continue;
+            }
             if (!s->dry) {
                 b.done = take_event(s);
                 if (!b.done) {
@@ -579,9 +627,13 @@ int mms_server_create(const mms_server_cfg* cfg_in, mms_server** out) {
     }
     // metadata slots at the start of the arena, sized for the largest batch
     const uint64_t nslots = (uint64_t)S * cfg.max_inflight;
-    s->slot_bytes = align_up(cfg.max_batch_requests * sizeof(mms::SegDesc)) +
-                    align_up(batch_tasks_bound(cfg.max_batch_keys, cfg.max_batch_requests) * sizeof(mms::TileTask)) +
-                    batch_table_bound(cfg.max_batch_keys, cfg.max_batch_requests);
+    uint32_t Kmin, Tmin;
+    tuning_floor(Kmin, Tmin);
+    const uint64_t nb = cfg.max_batch_keys, rb = cfg.max_batch_requests;
+    s->slot_bytes = align_up(rb * sizeof(mms::SegDesc)) +
+                    align_up(batch_tasks_bound(nb, rb, std::min<uint64_t>(nb, 0xFFFFFFFFull), Kmin, Tmin) *
+                             sizeof(mms::TileTask)) +
+                    batch_table_bound(nb, rb, Tmin);
     const uint64_t meta = nslots * s->slot_bytes;
     if (meta >= cfg.arena_bytes) {
         const unsigned long long need = meta;

@@ -19,7 +19,10 @@ def lib():
     if not os.path.exists(_lib.LIB_PATH):
         from paper_1702_07961_amd import build
         build.build()
-    return _lib.lib()
+    lib = _lib.lib()
+    lib.mms_set_tuning(None, 0)     # the built-in default, whatever table was loaded
+    yield lib
+    _lib.load_tuning(lib)
 
 
 def header_functions():
