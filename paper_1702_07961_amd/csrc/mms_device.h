@@ -22,6 +22,21 @@ namespace mms {
 
 constexpr int kWave = 64;
 constexpr uint32_t kSentKey = 0xFFFFFFFFu;
+
+// Global-memory views.  Accesses through generic pointers compile to FLAT
+// instructions, which count against the LDS counter as well as the vector
+// memory counter, so an LDS barrier would wait for them; through
+// address-space-1 pointers they become global_* instructions.
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef const __attribute__((address_space(1))) uint32_t cgu32;
+// four keys at a 4-byte aligned global address
+typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef const __attribute__((address_space(1))) u32x4a4 cgu32x4a4;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) u32x4 gu32x4;
+
+__device__ __forceinline__ gu32* gptr(uint32_t* p) { return (gu32*)p; }
+__device__ __forceinline__ cgu32* gptr(const uint32_t* p) { return (cgu32*)p; }
 constexpr uint32_t kSentTag = 0xFFFFFFFFu;
 
 template <bool P> struct Elem;
@@ -201,8 +216,8 @@ template <bool P> struct GlobalSinkLim {
     uint32_t lim;
     __device__ __forceinline__ void put(uint32_t i, const Elem<P>& e) const {
         if (i < lim) {
-            k[i] = e.k ^ flip;
-            if constexpr (P) v[i] = e.v;
+            gptr(k)[i] = e.k ^ flip;
+            if constexpr (P) gptr(v)[i] = e.v;
         }
     }
 };
@@ -302,6 +317,19 @@ template <> struct Xpose<8> {
     static constexpr uint32_t WORDS = 8 * RS;
 };
 
+// floor(a / b) for b > 0, a < 2^24 and a / b < 2^22, without the integer
+// division sequence.  a converts to float exactly; the reciprocal is within
+// one ulp and the product rounds once, so the estimate is within
+// (a / b) * 2^-22 < 1 of a / b and its truncation within one of the
+// quotient; one correction step each way makes it exact (q * b <= a + b
+// stays below 2^32).
+__device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
+    uint32_t q = (uint32_t)((float)a * __builtin_amdgcn_rcpf((float)b));
+    if (q * b > a) --q;
+    else if ((q + 1u) * b <= a) ++q;
+    return q;
+}
+
 // compiler and LDS ordering point for a wave's own scratch traffic
 __device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
@@ -400,16 +428,17 @@ struct GlobalSinkKeys {
     template <int EM>
     __device__ __forceinline__ void put_block(uint32_t pos0, uint32_t cnt, const uint32_t (&m)[EM], int lane) const {
         const uint32_t c_lim = min(cnt, lim > pos0 ? lim - pos0 : 0u);
+        gu32* g = gptr(y);
 #pragma unroll
         for (int c = 0; c < EM / 4; ++c) {
             const uint32_t t = (uint32_t)c * 256u + 4u * (uint32_t)lane;
             if (vec && t + 4u <= c_lim) {
-                *reinterpret_cast<uint4*>(y + pos0 + t) =
-                    make_uint4(m[4 * c] ^ flip, m[4 * c + 1] ^ flip, m[4 * c + 2] ^ flip, m[4 * c + 3] ^ flip);
+                *reinterpret_cast<gu32x4*>(g + pos0 + t) =
+                    u32x4{m[4 * c] ^ flip, m[4 * c + 1] ^ flip, m[4 * c + 2] ^ flip, m[4 * c + 3] ^ flip};
             } else {
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    if (t + (uint32_t)j < c_lim) y[pos0 + t + j] = m[4 * c + j] ^ flip;
+                    if (t + (uint32_t)j < c_lim) g[pos0 + t + j] = m[4 * c + j] ^ flip;
             }
         }
     }
@@ -484,7 +513,7 @@ template <int EM, class Sink>
 __device__ __forceinline__ void merge_level_keys(const uint32_t* X, const uint32_t* sbeg, const uint32_t* plen,
                                                  uint32_t nseg0, uint32_t lvl, const Sink& out, uint32_t* scr,
                                                  int wave, int nwaves, int lane) {
-    // all quantities below stay under 2^24, so 32-bit division is exact
+    // all quantities below stay under 2^22, the range of udiv_small
     const uint32_t total = plen[nseg0];               // keys in the level (gaps excluded)
     const uint32_t nseg = (nseg0 + (1u << lvl) - 1u) >> lvl;
     const uint32_t npairs = (nseg + 1u) / 2u;
@@ -506,10 +535,10 @@ __device__ __forceinline__ void merge_level_keys(const uint32_t* X, const uint32
         // waves whose midpoint (2v+1)*total/(2W) lies in the pair: v in [v0, v1),
         // v0 = smallest v with (2v+1)*total >= 2*W*plen[g0]
         const uint32_t n0 = 2u * W * plen[g0], n1 = 2u * W * plen[g2];
-        p_v0 = min(n0 <= total ? 0u : (n0 + total - 1u) / (2u * total), W);
-        p_v1 = min(n1 <= total ? 0u : (n1 + total - 1u) / (2u * total), W);
+        p_v0 = min(n0 <= total ? 0u : udiv_small(n0 + total - 1u, 2u * total), W);
+        p_v1 = min(n1 <= total ? 0u : udiv_small(n1 + total - 1u, 2u * total), W);
         // no midpoint inside: the wave whose equal share holds the pair start
-        p_own = min(plen[g0] * W / total, W - 1u);
+        p_own = min(udiv_small(plen[g0] * W, total), W - 1u);
     }
     for (uint32_t i = 0; i < npairs; ++i) {
         const uint32_t la = (uint32_t)__builtin_amdgcn_readlane((int)p_la, (int)i);
@@ -522,8 +551,8 @@ __device__ __forceinline__ void merge_level_keys(const uint32_t* X, const uint32
         if (v1 > v0) {
             if (w < v0 || w >= v1) continue;
             const uint32_t nw = v1 - v0, j = w - v0;
-            d0 = (s * j / nw) & ~3u;
-            d1 = j + 1 == nw ? s : (s * (j + 1) / nw) & ~3u;
+            d0 = udiv_small(s * j, nw) & ~3u;
+            d1 = j + 1 == nw ? s : udiv_small(s * (j + 1), nw) & ~3u;
         } else {
             if (w != (uint32_t)__builtin_amdgcn_readlane((int)p_own, (int)i)) continue;
             d0 = 0;
@@ -533,6 +562,40 @@ __device__ __forceinline__ void merge_level_keys(const uint32_t* X, const uint32
         const uint32_t aA = (uint32_t)__builtin_amdgcn_readlane((int)p_aA, (int)i);
         const uint32_t aB = (uint32_t)__builtin_amdgcn_readlane((int)p_aB, (int)i);
         merge_pair_range_keys<EM>(X, aA, la, aB, lb, d0, d1, out, aA, scr, lane);
+    }
+}
+
+// One merge level planned in advance: word 0 of (lvl, wave) holds the
+// wave's main range (pair index in bits 0..3, outputs [d0, d1) in bits
+// 4..17 and 18..31), word 1 a mask of further pairs the wave merges whole.
+// Pair i of level lvl merges segments 2i and 2i+1 (indices into
+// sbeg / plen, clamped to nseg0); the output of pair i starts at its first
+// segment's slot.
+template <int EM, class Sink>
+__device__ __forceinline__ void merge_level_planned(const uint32_t* X, const uint32_t* sbeg, const uint32_t* plen,
+                                                    const uint32_t* plan, uint32_t nseg0, uint32_t lvl,
+                                                    const Sink& out, uint32_t* scr, int wave, int lane) {
+    const uint32_t* pw = plan + 2u * (lvl * 16u + (uint32_t)wave);
+    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)pw[0]);
+    uint32_t own = (uint32_t)__builtin_amdgcn_readfirstlane((int)pw[1]);
+    auto run = [&](uint32_t i, uint32_t d0, uint32_t d1, bool whole) {
+        const uint32_t g0 = min((2u * i) << lvl, nseg0);
+        const uint32_t g1 = min((2u * i + 1u) << lvl, nseg0);
+        const uint32_t g2 = min((2u * i + 2u) << lvl, nseg0);
+        const uint32_t aA = (uint32_t)__builtin_amdgcn_readfirstlane((int)sbeg[g0]);
+        const uint32_t aB = (uint32_t)__builtin_amdgcn_readfirstlane((int)sbeg[g1]);
+        const uint32_t p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)plen[g0]);
+        const uint32_t p1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)plen[g1]);
+        const uint32_t p2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)plen[g2]);
+        const uint32_t la = p1 - p0, lb = p2 - p1;
+        if (whole) d1 = la + lb;
+        if (d0 < d1) merge_pair_range_keys<EM>(X, aA, la, aB, lb, d0, d1, out, aA, scr, lane);
+    };
+    run(w0 & 15u, (w0 >> 4) & 0x3FFFu, w0 >> 18, false);
+    while (own) {
+        const uint32_t i = (uint32_t)__builtin_ctz(own);
+        own &= own - 1u;
+        run(i, 0u, 0u, true);
     }
 }
 

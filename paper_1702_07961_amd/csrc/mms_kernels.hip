@@ -53,8 +53,8 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort(Phase ph, Bufs b, uint32_t
     for (int e = 0; e < E; ++e) {
         const uint32_t j = (uint32_t)wave * CH + (uint32_t)e * 64u + (uint32_t)lane;
         if (j < cnt) {
-            if constexpr (P) r[e] = Elem<P>{in_k[j] ^ flip, j, in_v[j]};
-            else r[e] = Elem<P>{in_k[j] ^ flip};
+            if constexpr (P) r[e] = Elem<P>{gptr(in_k)[j] ^ flip, j, gptr(in_v)[j]};
+            else r[e] = Elem<P>{gptr(in_k)[j] ^ flip};
         } else {
             r[e] = Elem<P>::sentinel();
         }
@@ -299,8 +299,8 @@ __global__ __launch_bounds__(W * 64) void k_merge_pairs(Phase ph, Bufs b, RoundA
         const uint32_t dst0 = seg0[k], len = seg0[k + 1] - dst0;
         const uint64_t src0 = gb + (uint64_t)k * L + start[k];
         for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) {
-            Xk[dst0 + j] = src_k[src0 + j];
-            Xv[dst0 + j] = src_v[src0 + j];
+            Xk[dst0 + j] = gptr(src_k)[src0 + j];
+            Xv[dst0 + j] = gptr(src_v)[src0 + j];
         }
     }
     lds_barrier();

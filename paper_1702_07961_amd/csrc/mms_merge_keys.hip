@@ -34,11 +34,15 @@ struct TileGeo {
     bool final_pass;  // last pass of the segment
 };
 
-__device__ __forceinline__ TileGeo tile_geo(const Phase& ph, const Bufs& b, uint64_t t, const RoundArgs& ra) {
+// lL = log2(L) (run lengths are T times a power of two)
+__device__ __forceinline__ TileGeo tile_geo(const Phase& ph, const Bufs& b, uint64_t t, const RoundArgs& ra,
+                                            int lL) {
     const TileRef tr = tile_ref(ph, b, t);
     TileGeo g;
-    // tile counts stay far below 2^32, so 32-bit division suffices
-    const uint32_t grp = tr.local / (uint32_t)ra.tpg;
+    // a tile index is below 2^23 (n < 2^32, Tout >= 1024, plus one per
+    // group) and the quotient below 2^22 unless tpg = 1, where the estimate
+    // is exact; a divisor above the index gives 0, so it may be clamped
+    const uint32_t grp = udiv_small(tr.local, (uint32_t)min<uint64_t>(ra.tpg, (1u << 23)));
     const uint64_t i = tr.local - (uint64_t)grp * ra.tpg;
     const uint64_t span = (uint64_t)ra.K * ra.L;
     const uint64_t gb = (uint64_t)grp * span;
@@ -46,7 +50,7 @@ __device__ __forceinline__ TileGeo tile_geo(const Phase& ph, const Bufs& b, uint
     g.dst = tr.dst_k;
     g.gb = gb;
     g.glen = min(span, tr.n - gb);
-    g.Kg = (uint32_t)((g.glen + ra.L - 1) / ra.L);
+    g.Kg = (uint32_t)((g.glen + ra.L - 1) >> lL);
     g.obeg = i * (uint64_t)ra.Tout;
     g.cnt = (uint32_t)min<uint64_t>(ra.Tout, g.glen - g.obeg);
     g.first = i == 0;
@@ -55,18 +59,30 @@ __device__ __forceinline__ TileGeo tile_geo(const Phase& ph, const Bufs& b, uint
     return g;
 }
 
-// Split indices of tile t for run `lane` (wave 0, lanes < Kg): start s, end e.
+// Split indices of tile t for run `lane` (lanes < Kg): start s, end e.
+// The table rows t and t+1 are read with scalar loads (the table was written
+// by an earlier launch), so the wave does not wait on its own outstanding
+// vector memory traffic, which includes the previous tile's stores.
+typedef const __attribute__((address_space(4))) uint32_t* ScalarU32;
+
 __device__ __forceinline__ void load_split(const uint32_t* __restrict__ table, uint64_t t, const TileGeo& g,
                                            uint64_t L, uint32_t K, int lane, uint32_t& s, uint32_t& e) {
+    const ScalarU32 tc = (ScalarU32)table;
+    const uint64_t r0 = t * K, r1 = r0 + K;
     s = 0;
     e = 0;
-    if ((uint32_t)lane < g.Kg) {
-        const uint32_t nk = (uint32_t)min(L, g.glen - (uint64_t)lane * L);
-        s = g.first ? 0u : table[t * K + (uint32_t)lane];
-        e = g.last ? nk : table[(t + 1) * K + (uint32_t)lane];
-        // guards for memory safety only; exact splits satisfy s <= e <= nk
-        s = min(s, nk);
-        e = min(max(e, s), nk);
+#pragma unroll
+    for (uint32_t k = 0; k < kMaxFanout; ++k) {
+        if (k < g.Kg) {
+            const uint32_t nk = (uint32_t)min(L, g.glen - (uint64_t)k * L);
+            uint32_t sk = g.first ? 0u : tc[r0 + k];
+            uint32_t ek = g.last ? nk : tc[r1 + k];
+            // guards for memory safety only; exact splits satisfy s <= e <= nk
+            sk = min(sk, nk);
+            ek = min(max(ek, sk), nk);
+            s = (uint32_t)lane == k ? sk : s;
+            e = (uint32_t)lane == k ? ek : e;
+        }
     }
 }
 
@@ -76,9 +92,11 @@ struct Meta {
     uint32_t* start;
     uint32_t* plen;
     uint32_t* sbeg;
-    uint32_t* cseg;   // [kToutKeys/64]: piece holding position 64*c of the tile
+    uint32_t* plan;   // [4 levels][16 waves][2]: each wave's work per level
+    uint32_t* cseg;   // piece whose LDS slots hold word 64*c (slot coordinates)
 };
-constexpr uint32_t kMetaWords = 3u * 17u + kToutKeys / 64u;
+constexpr uint32_t kPlanWords = 4u * 16u * 2u;
+constexpr uint32_t kMetaWords = 3u * 17u + kPlanWords + (kToutKeys + 4u * kMaxFanout) / 64u + 1u;
 
 __device__ __forceinline__ uint32_t excl_scan16(uint32_t x, int lane) {
     uint32_t incl = x;
@@ -90,6 +108,50 @@ __device__ __forceinline__ uint32_t excl_scan16(uint32_t x, int lane) {
     return incl - x;
 }
 
+// Work of every wave at every merge level of the tile, one (level, wave) per
+// lane (lane = 16 * level + wave).  Pair i of level l gets the waves whose
+// equal shares of the level's outputs have their midpoints inside it,
+// (2w+1) * total / (2W) in [plen[g0], plen[g2]), and they split it evenly at
+// multiples of 4; a pair holding no midpoint goes whole to the wave whose
+// share holds its start.  No quantity reaches 2^22 (udiv_small's range).
+template <int W>
+__device__ __forceinline__ void build_plan(const Meta& m, uint32_t Kg, uint32_t total, int lane) {
+    const uint32_t l = (uint32_t)lane >> 4, w = (uint32_t)lane & 15u;
+    uint32_t nlev = 0;
+    while ((1u << nlev) < Kg) ++nlev;
+    const bool act = w < (uint32_t)W && l < nlev;
+    const uint32_t nseg = act ? (Kg + (1u << l) - 1u) >> l : 0u;
+    const uint32_t npairs = (nseg + 1u) >> 1;
+    const uint32_t mid2 = (2u * w + 1u) * total;           // 2W * midpoint
+    uint32_t iw = 0;
+    for (uint32_t i = 1; i < npairs; ++i)
+        if (2u * (uint32_t)W * m.plen[min((2u * i) << l, Kg)] <= mid2) iw = i;
+    const uint64_t grp = 0xFFFFull << (16u * (l & 3u));
+    uint32_t v0 = 0, nw = 1, own = 0;
+    for (uint32_t i = 0; i < 8u; ++i) {
+        const uint64_t mi = __ballot(act && i < npairs && iw == i) & grp;
+        if (act && i == iw && mi) {
+            v0 = (uint32_t)__builtin_ctzll(mi) - 16u * l;
+            nw = (uint32_t)__popcll(mi);
+        }
+        if (act && i < npairs && mi == 0ull && total) {
+            const uint32_t p0 = m.plen[min((2u * i) << l, Kg)];
+            const uint32_t o = min(udiv_small(p0 * (uint32_t)W, total), (uint32_t)W - 1u);
+            if (o == w) own |= 1u << i;
+        }
+    }
+    if (act) {
+        const uint32_t p0 = m.plen[min((2u * iw) << l, Kg)];
+        const uint32_t p2 = m.plen[min((2u * iw + 2u) << l, Kg)];
+        const uint32_t sz = p2 - p0, j = w - v0;
+        const uint32_t d0 = total ? udiv_small(sz * j, nw) & ~3u : 0u;
+        const uint32_t d1 = !total ? 0u : (j + 1u == nw ? sz : udiv_small(sz * (j + 1u), nw) & ~3u);
+        m.plan[2u * (uint32_t)lane] = iw | (d0 << 4) | (d1 << 18);
+        m.plan[2u * (uint32_t)lane + 1u] = own;
+    }
+}
+
+template <int W>
 __device__ __forceinline__ void build_meta(const Meta& m, uint32_t s, uint32_t e, const TileGeo& g, int lane) {
     const bool own = (uint32_t)lane < g.Kg;
     uint32_t len = own ? e - s : 0u;
@@ -110,21 +172,22 @@ __device__ __forceinline__ void build_meta(const Meta& m, uint32_t s, uint32_t e
         m.sbeg[g.Kg] = tot_sb;
     }
     lds_wave_sync();
-    // chunk table: largest k < Kg with plen[k] <= 64*c
-    for (uint32_t c = (uint32_t)lane; c * 64u < tot_pl; c += 64u) {
+    // chunk table: largest k < Kg with sbeg[k] <= 64*c
+    for (uint32_t c = (uint32_t)lane; c * 64u < tot_sb; c += 64u) {
         uint32_t lo = 0, hi = g.Kg;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (m.plen[mid] <= c * 64u) lo = mid;
+            if (m.sbeg[mid] <= c * 64u) lo = mid;
             else hi = mid;
         }
         m.cseg[c] = lo;
     }
+    build_plan<W>(m, g.Kg, tot_pl, lane);
 }
 
 }  // namespace
 
-template <int EM, int W, int PF>
+template <int EM, int W, int PC>
 __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundArgs ra,
                                                        const uint32_t* __restrict__ table, uint32_t flip) {
     constexpr uint32_t NT = W * 64;
@@ -139,7 +202,7 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
     uint32_t* mbase = scr + W * Xpose<EM>::WORDS;     // two piece tables of kMetaWords
     auto meta = [&](int which) {
         uint32_t* mb = mbase + kMetaWords * (uint32_t)which;
-        return Meta{mb, mb + 17, mb + 34, mb + 51};
+        return Meta{mb, mb + 17, mb + 34, mb + 51, mb + 51 + kPlanWords};
     };
 
     const int lane = threadIdx.x & 63;
@@ -150,65 +213,79 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
 
     uint64_t t = blockIdx.x;
     if (t >= tiles) return;
+    const int lL = __builtin_ctzll(L);
 
-    // registers of the prefetch stage
-    uint32_t pf_val[PF];
-    uint32_t pf_dst[PF];
+    // registers of the prefetch stage: chunks of 4 LDS slots per thread
+    uint4 pf_val[PC];
+    uint32_t pf_dst[PC];
     uint32_t nx_s = 0, nx_e = 0;   // wave 0: split indices of the tile after next
 
-    auto issue_loads = [&](uint64_t tt, const Meta& m) {
-        const TileGeo g = tile_geo(ph, b, tt, ra);
-        const uint32_t* src = g.src;
+    // Chunk P (a multiple of 4 in LDS slot coordinates) lies in piece k with
+    // sbeg[k] <= P < sbeg[k] + len_k rounded up to 4, so off = P - sbeg[k] <
+    // len_k: its first key exists; it is read with one 16-byte load when all
+    // four do (global addresses are only 4-byte aligned), else key by key.
+    // Slots past a piece's end are padding that no merge step reads.
+    auto issue_loads = [&](const TileGeo& g, const Meta& m) {
+        const uint32_t slots = m.sbeg[g.Kg];
 #pragma unroll
-        for (int r = 0; r < PF; ++r) {
-            const uint32_t j = (uint32_t)r * NT + tid;
+        for (int r = 0; r < PC; ++r) {
+            const uint32_t P = 4u * ((uint32_t)r * NT + tid);
             pf_dst[r] = 0xFFFFFFFFu;
-            if (j < m.plen[g.Kg]) {
-                uint32_t lo = m.cseg[j >> 6];        // largest k with plen[k] <= j
-                while (lo + 1u < g.Kg && m.plen[lo + 1u] <= j) ++lo;
-                const uint32_t off = j - m.plen[lo];
-                pf_val[r] = src[g.gb + (uint64_t)lo * L + m.start[lo] + off];
-                pf_dst[r] = m.sbeg[lo] + off;
+            if (P < slots) {
+                uint32_t k = m.cseg[P >> 6];
+                while (k + 1u < g.Kg && m.sbeg[k + 1u] <= P) ++k;
+                const uint32_t off = P - m.sbeg[k];
+                const uint32_t len = m.plen[k + 1u] - m.plen[k];
+                cgu32* sp = gptr(g.src) + g.gb + (uint64_t)k * L + m.start[k] + off;
+                if (off + 4u <= len) {
+                    const u32x4a4 v = *reinterpret_cast<cgu32x4a4*>(sp);
+                    pf_val[r] = make_uint4(v.x, v.y, v.z, v.w);
+                } else {
+                    pf_val[r].x = sp[0];
+                    pf_val[r].y = off + 1u < len ? sp[1] : 0u;
+                    pf_val[r].z = off + 2u < len ? sp[2] : 0u;
+                    pf_val[r].w = 0u;
+                }
+                pf_dst[r] = P;
             }
         }
     };
     auto store_loads = [&](uint32_t* X) {
 #pragma unroll
-        for (int r = 0; r < PF; ++r)
-            if (pf_dst[r] != 0xFFFFFFFFu) X[pf_dst[r]] = pf_val[r];
+        for (int r = 0; r < PC; ++r)
+            if (pf_dst[r] != 0xFFFFFFFFu) *reinterpret_cast<uint4*>(X + pf_dst[r]) = pf_val[r];
     };
 
     // prologue: piece table and keys of the first tile, split of the second
+    TileGeo g = tile_geo(ph, b, t, ra, lL);
     {
-        const TileGeo g0 = tile_geo(ph, b, t, ra);
         if (wave == 0) {
             uint32_t s, e;
-            load_split(table, t, g0, L, K, lane, s, e);
-            build_meta(meta(0), s, e, g0, lane);
-            if (t + G < tiles) load_split(table, t + G, tile_geo(ph, b, t + G, ra), L, K, lane, nx_s, nx_e);
+            load_split(table, t, g, L, K, lane, s, e);
+            build_meta<W>(meta(0), s, e, g, lane);
+            if (t + G < tiles) load_split(table, t + G, tile_geo(ph, b, t + G, ra, lL), L, K, lane, nx_s, nx_e);
         }
         lds_barrier();
-        issue_loads(t, meta(0));
+        issue_loads(g, meta(0));
         store_loads(bufA);
         lds_barrier();
     }
 
     int cur = 0;
     for (;;) {
-        const TileGeo g = tile_geo(ph, b, t, ra);
         uint32_t* dst = g.dst;
         const uint32_t flip_out = g.final_pass ? flip : 0u;
         const Meta mc = meta(cur);
         const Meta mn = meta(cur ^ 1);
         const uint64_t tn = t + G;
         const bool has_next = tn < tiles;
+        const TileGeo gn = has_next ? tile_geo(ph, b, tn, ra, lL) : g;
 
         // wave 0: piece table of the next tile, split indices of the one after
         if (wave == 0 && has_next) {
-            const TileGeo gn = tile_geo(ph, b, tn, ra);
-            build_meta(mn, nx_s, nx_e, gn, lane);
+            build_meta<W>(mn, nx_s, nx_e, gn, lane);
             if (tn + G < tiles)
-                load_split(table, tn + G, tile_geo(ph, b, tn + G, ra), L, K, lane, nx_s, nx_e);
+                load_split(table, tn + G, tile_geo(ph, b, tn + G, ra, lL), L, K, lane, nx_s, nx_e);
         }
 
         uint32_t* X = bufA;
@@ -218,26 +295,26 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
         if (g.Kg == 1) {
             lds_barrier();
             if (has_next) {
-                issue_loads(tn, mn);
+                issue_loads(gn, mn);
                 issued = true;
             }
-            for (uint32_t j = tid; j < g.cnt; j += NT) dst[obase + j] = X[j] ^ flip_out;
+            for (uint32_t j = tid; j < g.cnt; j += NT) gptr(dst)[obase + j] = X[j] ^ flip_out;
         } else {
             const bool vec = ((uintptr_t)(dst + obase) & 15u) == 0;
             for (uint32_t lvl = 0; (1u << lvl) < g.Kg; ++lvl) {
                 const bool last = (2u << lvl) >= g.Kg;
                 if (last) {
                     GlobalSinkKeys out{dst + obase, flip_out, g.cnt, vec};
-                    merge_level_keys<EM>(X, mc.sbeg, mc.plen, g.Kg, lvl, out, wscr, wave, W, lane);
+                    merge_level_planned<EM>(X, mc.sbeg, mc.plen, mc.plan, g.Kg, lvl, out, wscr, wave, lane);
                 } else {
                     LdsSinkKeys out{Y};
-                    merge_level_keys<EM>(X, mc.sbeg, mc.plen, g.Kg, lvl, out, wscr, wave, W, lane);
+                    merge_level_planned<EM>(X, mc.sbeg, mc.plen, mc.plan, g.Kg, lvl, out, wscr, wave, lane);
                 }
                 lds_barrier();
                 // the next tile's piece table is visible now; its loads overlap
                 // the remaining levels
                 if (!issued && has_next) {
-                    issue_loads(tn, mn);
+                    issue_loads(gn, mn);
                     issued = true;
                 }
                 uint32_t* tmp = X; X = Y; Y = tmp;
@@ -248,6 +325,7 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
         store_loads(bufA);
         lds_barrier();
         t = tn;
+        g = gn;
         cur ^= 1;
     }
 }
@@ -259,9 +337,11 @@ static hipError_t allow_lds(const void* f, size_t bytes) {
 template <int EM, int W>
 static hipError_t launch_variant(const Phase& ph, const Bufs& b, const RoundArgs& ra, const uint32_t* table,
                                  uint32_t flip, unsigned grid, hipStream_t s) {
-    constexpr int PF = (int)((kToutKeys + W * 64 - 1) / (W * 64));
+    // chunks of 4 slots per thread: a tile holds at most kToutKeys keys plus
+    // up to 3 padding slots per piece
+    constexpr int PC = (int)((kToutKeys + 4u * kMaxFanout + 4u * W * 64u - 1u) / (4u * W * 64u));
     const size_t lds = (2u * (ra.Tout + 4u * ra.K) + W * Xpose<EM>::WORDS + 2u * kMetaWords) * sizeof(uint32_t);
-    hipError_t e = allow_lds((const void*)k_merge_keys<EM, W, PF>, lds);
+    hipError_t e = allow_lds((const void*)k_merge_keys<EM, W, PC>, lds);
     if (e != hipSuccess) return e;
     // persistent grid: as many workgroups as fit in the LDS of `grid` CUs
     int dev = 0, lds_cu = 0;
@@ -272,7 +352,7 @@ static hipError_t launch_variant(const Phase& ph, const Bufs& b, const RoundArgs
     const uint64_t per_cu = (uint64_t)lds_cu / lds > 0 ? (uint64_t)lds_cu / lds : 1;
     const uint64_t want = (uint64_t)grid * per_cu;
     const unsigned blocks = (unsigned)(want < ph.tiles ? want : ph.tiles);
-    hipLaunchKernelGGL((k_merge_keys<EM, W, PF>), dim3(blocks), dim3(W * 64), lds, s, ph, b, ra, table, flip);
+    hipLaunchKernelGGL((k_merge_keys<EM, W, PC>), dim3(blocks), dim3(W * 64), lds, s, ph, b, ra, table, flip);
     return hipGetLastError();
 }
 
