@@ -154,7 +154,8 @@ int mms_segmented_sort(const uint32_t* d_kin, uint32_t* d_kout, const uint32_t* 
  * is the merge fan-out K (power of two, 2..16), merge_tile the keys-only
  * merge output tile (multiple of 256, 1024..8192), variant the merge kernel
  * shape (0: 64x16-key blocks, 8 waves; 1: 64x8-key blocks, 16 waves;
- * 2: 64x8-key blocks, 8 waves).  count == 0 restores the built-in default
+ * 2: 64x8-key blocks, 8 waves; 3: as 2 with two workgroups per compute
+ * unit, for merge tiles up to about 6656).  count == 0 restores the built-in default
  * (K = 16, 8192, variant 0, overridable by MMS_FANOUT / MMS_TOUT /
  * MMS_MERGE_VARIANT).  Workspace sizes depend on the table: query
  * mms_workspace_bytes after changing it.  Process-wide, thread-safe.

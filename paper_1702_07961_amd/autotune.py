@@ -22,8 +22,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(PKG, "tuning_mi355x.json")
 
 FANOUTS = [4, 8, 16]
-TILES = [2048, 4096, 8192]
-VARIANTS = [0, 1, 2]
+TILES = [2048, 4096, 6144, 7168, 8192]
+VARIANTS = [0, 1, 2, 3]
 
 
 def candidates(log2n: int):

@@ -109,7 +109,7 @@ Tune env_default() {
 
 bool valid_tune(uint32_t K, uint32_t Tout, int variant) {
     return K >= 2 && K <= mms::kMaxFanout && (K & (K - 1)) == 0 && Tout >= 1024 && Tout <= mms::kToutKeys &&
-           Tout % 256 == 0 && variant >= 0 && variant <= 2;
+           Tout % 256 == 0 && variant >= 0 && variant <= 3;
 }
 
 Tune tune_for(uint64_t n, bool pairs) {

@@ -145,7 +145,9 @@ hipError_t launch_merge_pairs(const Phase& ph, const Bufs& b, const RoundArgs& r
 
 // Keys-only merge round, persistent: `grid` compute units' worth of
 // workgroups walk the phase's tiles.  variant 0: 64x16-key blocks, 8 waves;
-// 1: 64x8-key blocks, 16 waves; 2: 64x8, 8 waves.
+// 1: 64x8-key blocks, 16 waves; 2: 64x8, 8 waves; 3: 64x8, 8 waves, two
+// workgroups per compute unit (registers capped for it; the merge tile must
+// be small enough for two workgroups' LDS).
 hipError_t launch_merge_keys(const Phase& ph, const Bufs& b, const RoundArgs& ra, const uint32_t* table,
                              uint32_t flip, unsigned grid, int variant, hipStream_t s);
 

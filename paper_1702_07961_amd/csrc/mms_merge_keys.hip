@@ -7,10 +7,12 @@
 // level, with the conflict-free block step of merge_level_keys (log2 K
 // levels: X->Y->X->...); the last level stores straight to memory.
 //
-// Memory latency is hidden by a two-stage prefetch: while tile t is merged,
-// the keys of tile t+G are loaded into registers (each thread holds
-// ceil(Tout / threads) of them together with their LDS destinations), and
-// wave 0 already holds the split indices of tile t+2G.
+// Memory latency is hidden by a three-stage pipeline: as tile t starts, the
+// keys of tile t+G are loaded into registers in 16-byte chunks (each thread
+// holds a few chunks with their LDS destinations) and land in the LDS buffer
+// that tile t's last level does not read; wave 0 meanwhile builds the piece
+// table and per-level wave plan of tile t+2G from split indices it fetched
+// one tile earlier with scalar loads.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,9 +31,11 @@ struct TileGeo {
     uint64_t obeg;    // tile start inside the group
     uint32_t Kg;      // runs in the group
     uint32_t cnt;     // outputs of the tile
-    bool first;       // first tile of its group
-    bool last;        // last tile of its group
-    bool final_pass;  // last pass of the segment
+    // flags as full words: the struct is copied across loop iterations and
+    // must stay in registers
+    uint32_t first;       // first tile of its group
+    uint32_t last;        // last tile of its group
+    uint32_t final_pass;  // last pass of the segment
 };
 
 // lL = log2(L) (run lengths are T times a power of two)
@@ -53,9 +57,9 @@ __device__ __forceinline__ TileGeo tile_geo(const Phase& ph, const Bufs& b, uint
     g.Kg = (uint32_t)((g.glen + ra.L - 1) >> lL);
     g.obeg = i * (uint64_t)ra.Tout;
     g.cnt = (uint32_t)min<uint64_t>(ra.Tout, g.glen - g.obeg);
-    g.first = i == 0;
-    g.last = g.obeg + ra.Tout >= g.glen;
-    g.final_pass = tr.final_pass;
+    g.first = i == 0 ? 1u : 0u;
+    g.last = g.obeg + ra.Tout >= g.glen ? 1u : 0u;
+    g.final_pass = tr.final_pass ? 1u : 0u;
     return g;
 }
 
@@ -187,8 +191,10 @@ __device__ __forceinline__ void build_meta(const Meta& m, uint32_t s, uint32_t e
 
 }  // namespace
 
-template <int EM, int W, int PC>
-__global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundArgs ra,
+// MINW: waves per SIMD the register allocation must allow (HIP's second
+// launch bound); 4 with 8-wave workgroups lets two workgroups share a CU.
+template <int EM, int W, int PC, int MINW>
+__global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, RoundArgs ra,
                                                        const uint32_t* __restrict__ table, uint32_t flip) {
     constexpr uint32_t NT = W * 64;
     const uint64_t L = ra.L;
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
     uint32_t* bufA = smem;
     uint32_t* bufB = smem + cap;
     uint32_t* scr = smem + 2 * cap;
-    uint32_t* mbase = scr + W * Xpose<EM>::WORDS;     // two piece tables of kMetaWords
+    uint32_t* mbase = scr + W * Xpose<EM>::WORDS;     // three piece tables of kMetaWords
     auto meta = [&](int which) {
         uint32_t* mb = mbase + kMetaWords * (uint32_t)which;
         return Meta{mb, mb + 17, mb + 34, mb + 51, mb + 51 + kPlanWords};
@@ -218,7 +224,7 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
     // registers of the prefetch stage: chunks of 4 LDS slots per thread
     uint4 pf_val[PC];
     uint32_t pf_dst[PC];
-    uint32_t nx_s = 0, nx_e = 0;   // wave 0: split indices of the tile after next
+    uint32_t nx_s = 0, nx_e = 0;   // wave 0: split indices of tile t+2G (at loop start)
 
     // Chunk P (a multiple of 4 in LDS slot coordinates) lies in piece k with
     // sbeg[k] <= P < sbeg[k] + len_k rounded up to 4, so off = P - sbeg[k] <
@@ -257,13 +263,24 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
     };
 
     // prologue: piece table and keys of the first tile, split of the second
+    // Pipeline: while tile t is merged, the keys of tile t+G are in flight
+    // (issued as tile t starts) and wave 0 prepares the piece table of tile
+    // t+2G from split indices it loaded one tile earlier.  Three piece tables
+    // rotate (tiles t, t+G, t+2G).
+    auto nxt = [](int i) { return i == 2 ? 0 : i + 1; };
     TileGeo g = tile_geo(ph, b, t, ra, lL);
+    TileGeo g1 = tile_geo(ph, b, t + G < tiles ? t + G : t, ra, lL);
     {
         if (wave == 0) {
             uint32_t s, e;
             load_split(table, t, g, L, K, lane, s, e);
             build_meta<W>(meta(0), s, e, g, lane);
-            if (t + G < tiles) load_split(table, t + G, tile_geo(ph, b, t + G, ra, lL), L, K, lane, nx_s, nx_e);
+            if (t + G < tiles) {
+                load_split(table, t + G, g1, L, K, lane, s, e);
+                build_meta<W>(meta(1), s, e, g1, lane);
+                if (t + 2 * G < tiles)
+                    load_split(table, t + 2 * G, tile_geo(ph, b, t + 2 * G, ra, lL), L, K, lane, nx_s, nx_e);
+            }
         }
         lds_barrier();
         issue_loads(g, meta(0));
@@ -272,37 +289,51 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
     }
 
     int cur = 0;
+    uint32_t* in = bufA;      // LDS buffer holding the current tile's pieces
+    uint32_t* other = bufB;
     for (;;) {
         uint32_t* dst = g.dst;
         const uint32_t flip_out = g.final_pass ? flip : 0u;
         const Meta mc = meta(cur);
-        const Meta mn = meta(cur ^ 1);
-        const uint64_t tn = t + G;
-        const bool has_next = tn < tiles;
-        const TileGeo gn = has_next ? tile_geo(ph, b, tn, ra, lL) : g;
+        const Meta mn = meta(nxt(cur));
+        const uint64_t tn = t + G, t2 = t + 2 * G;
+        const bool has_next = tn < tiles, has2 = t2 < tiles;
 
-        // wave 0: piece table of the next tile, split indices of the one after
-        if (wave == 0 && has_next) {
-            build_meta<W>(mn, nx_s, nx_e, gn, lane);
-            if (tn + G < tiles)
-                load_split(table, tn + G, tile_geo(ph, b, tn + G, ra, lL), L, K, lane, nx_s, nx_e);
+        // the next tile's keys go in flight now and land during the last level
+        bool issued = false, stored = false;
+        if (has_next) {
+            issue_loads(g1, mn);
+            issued = true;
+        }
+        // geometry of tile t+2G (of tile t when there is none: no select
+        // between structs is needed)
+        const TileGeo g2 = tile_geo(ph, b, has2 ? t2 : t, ra, lL);
+        // wave 0: piece table of tile t+2G, split indices of tile t+3G
+        if (wave == 0 && has2) {
+            build_meta<W>(meta(nxt(nxt(cur))), nx_s, nx_e, g2, lane);
+            if (t2 + G < tiles)
+                load_split(table, t2 + G, tile_geo(ph, b, t2 + G, ra, lL), L, K, lane, nx_s, nx_e);
         }
 
-        uint32_t* X = bufA;
-        uint32_t* Y = bufB;
+        uint32_t* X = in;
+        uint32_t* Y = other;
         const uint64_t obase = g.gb + g.obeg;
-        bool issued = false;
+        uint32_t nlev = 0;
+        while ((1u << nlev) < g.Kg) ++nlev;
         if (g.Kg == 1) {
-            lds_barrier();
-            if (has_next) {
-                issue_loads(gn, mn);
-                issued = true;
-            }
             for (uint32_t j = tid; j < g.cnt; j += NT) gptr(dst)[obase + j] = X[j] ^ flip_out;
         } else {
             const bool vec = ((uintptr_t)(dst + obase) & 15u) == 0;
-            for (uint32_t lvl = 0; (1u << lvl) < g.Kg; ++lvl) {
-                const bool last = (2u << lvl) >= g.Kg;
+            for (uint32_t lvl = 0; lvl < nlev; ++lvl) {
+                const bool last = lvl + 1u == nlev;
+                // from the second level on, the last level reads the buffer the
+                // level before wrote, and the other one is free: the next
+                // tile's keys go there, and the barrier after the last level
+                // publishes them
+                if (last && lvl > 0 && issued) {
+                    store_loads(Y);
+                    stored = true;
+                }
                 if (last) {
                     GlobalSinkKeys out{dst + obase, flip_out, g.cnt, vec};
                     merge_level_planned<EM>(X, mc.sbeg, mc.plen, mc.plan, g.Kg, lvl, out, wscr, wave, lane);
@@ -311,22 +342,24 @@ __global__ __launch_bounds__(W * 64) void k_merge_keys(Phase ph, Bufs b, RoundAr
                     merge_level_planned<EM>(X, mc.sbeg, mc.plen, mc.plan, g.Kg, lvl, out, wscr, wave, lane);
                 }
                 lds_barrier();
-                // the next tile's piece table is visible now; its loads overlap
-                // the remaining levels
-                if (!issued && has_next) {
-                    issue_loads(gn, mn);
-                    issued = true;
-                }
                 uint32_t* tmp = X; X = Y; Y = tmp;
             }
         }
         if (!has_next) break;
-        lds_barrier();        // every wave is done reading this tile's LDS
-        store_loads(bufA);
-        lds_barrier();
+        if (stored) {
+            // after the level loop (and its final swap) X holds the next
+            // tile's keys and Y is the buffer the last level read
+            in = X;
+            other = Y;
+        } else {
+            lds_barrier();        // every wave is done reading this tile's LDS
+            store_loads(in);
+            lds_barrier();
+        }
         t = tn;
-        g = gn;
-        cur ^= 1;
+        g = g1;
+        g1 = g2;
+        cur = nxt(cur);
     }
 }
 
@@ -334,14 +367,14 @@ static hipError_t allow_lds(const void* f, size_t bytes) {
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int EM, int W>
+template <int EM, int W, int MINW>
 static hipError_t launch_variant(const Phase& ph, const Bufs& b, const RoundArgs& ra, const uint32_t* table,
                                  uint32_t flip, unsigned grid, hipStream_t s) {
     // chunks of 4 slots per thread: a tile holds at most kToutKeys keys plus
     // up to 3 padding slots per piece
     constexpr int PC = (int)((kToutKeys + 4u * kMaxFanout + 4u * W * 64u - 1u) / (4u * W * 64u));
-    const size_t lds = (2u * (ra.Tout + 4u * ra.K) + W * Xpose<EM>::WORDS + 2u * kMetaWords) * sizeof(uint32_t);
-    hipError_t e = allow_lds((const void*)k_merge_keys<EM, W, PC>, lds);
+    const size_t lds = (2u * (ra.Tout + 4u * ra.K) + W * Xpose<EM>::WORDS + 3u * kMetaWords) * sizeof(uint32_t);
+    hipError_t e = allow_lds((const void*)k_merge_keys<EM, W, PC, MINW>, lds);
     if (e != hipSuccess) return e;
     // persistent grid: as many workgroups as fit in the LDS of `grid` CUs
     int dev = 0, lds_cu = 0;
@@ -352,7 +385,7 @@ static hipError_t launch_variant(const Phase& ph, const Bufs& b, const RoundArgs
     const uint64_t per_cu = (uint64_t)lds_cu / lds > 0 ? (uint64_t)lds_cu / lds : 1;
     const uint64_t want = (uint64_t)grid * per_cu;
     const unsigned blocks = (unsigned)(want < ph.tiles ? want : ph.tiles);
-    hipLaunchKernelGGL((k_merge_keys<EM, W, PC>), dim3(blocks), dim3(W * 64), lds, s, ph, b, ra, table, flip);
+    hipLaunchKernelGGL((k_merge_keys<EM, W, PC, MINW>), dim3(blocks), dim3(W * 64), lds, s, ph, b, ra, table, flip);
     return hipGetLastError();
 }
 
@@ -360,9 +393,10 @@ hipError_t launch_merge_keys(const Phase& ph, const Bufs& b, const RoundArgs& ra
                              uint32_t flip, unsigned grid, int variant, hipStream_t s) {
     if (ra.Tout > kToutKeys || ra.K > kMaxFanout || ra.Tout % 4 || ra.L % 4) return hipErrorInvalidValue;
     if (ph.tiles == 0) return hipSuccess;
-    if (variant == 1) return launch_variant<8, 16>(ph, b, ra, table, flip, grid, s);
-    if (variant == 2) return launch_variant<8, 8>(ph, b, ra, table, flip, grid, s);
-    return launch_variant<16, 8>(ph, b, ra, table, flip, grid, s);
+    if (variant == 1) return launch_variant<8, 16, 1>(ph, b, ra, table, flip, grid, s);
+    if (variant == 2) return launch_variant<8, 8, 1>(ph, b, ra, table, flip, grid, s);
+    if (variant == 3) return launch_variant<8, 8, 4>(ph, b, ra, table, flip, grid, s);
+    return launch_variant<16, 8, 1>(ph, b, ra, table, flip, grid, s);
 }
 
 }  // namespace mms
