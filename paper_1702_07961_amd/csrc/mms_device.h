@@ -83,8 +83,28 @@ __device__ __forceinline__ Elem<true> pick(const Elem<true>& mine, const Elem<tr
     return r;
 }
 
+// Value of lane (lane ^ m).  When m is a constant (after loop unrolling)
+// this folds to one exchange: DPP within a row of 16 lanes
+// (quad permutes, row mirrors, rotate by 8), a ds_swizzle inside 32 lanes,
+// and ds_bpermute across the halves of the wave.
 __device__ __forceinline__ uint32_t shfl_xor_u32(uint32_t x, int m) {
-    return (uint32_t)__shfl_xor((int)x, m, kWave);
+    const int v = (int)x;
+    // a mask only known at run time (a loop the compiler kept rolled) takes
+    // the general permute rather than a branch per exchange
+    if (!__builtin_constant_p(m)) return (uint32_t)__shfl_xor(v, m, kWave);
+    switch (m) {
+        case 1: return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);    // quad_perm [1,0,3,2]
+        case 2: return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);    // quad_perm [2,3,0,1]
+        case 3: return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x1B, 0xF, 0xF, false);    // quad_perm [3,2,1,0]
+        case 7: return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);   // row_half_mirror
+        case 8: return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);   // row_ror:8
+        case 15: return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false);  // row_mirror
+        // bit-mask swizzle inside 32 lanes: and 0x1F, or 0, xor m
+        case 4: return (uint32_t)__builtin_amdgcn_ds_swizzle(v, 0x1F | (4 << 10));
+        case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle(v, 0x1F | (16 << 10));
+        case 31: return (uint32_t)__builtin_amdgcn_ds_swizzle(v, 0x1F | (31 << 10));
+        default: return (uint32_t)__shfl_xor(v, m, kWave);
+    }
 }
 __device__ __forceinline__ Elem<false> shfl_xor(const Elem<false>& e, int m) { return {shfl_xor_u32(e.k, m)}; }
 __device__ __forceinline__ Elem<true> shfl_xor(const Elem<true>& e, int m) {
