@@ -114,12 +114,6 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort(Phase ph, Bufs b, uint32_t
 // at h = 1 the bounds meet: c_k = lo_k = hi_k.  Ties are ordered by (key,
 // run, position), the stable order.
 // ===========================================================================
-__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, uint32_t l) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (int)l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), (int)l);
-    return ((uint64_t)hi << 32) | lo;
-}
-
 // Inclusive sum over the 16 lanes of each row (DPP row shifts).
 __device__ __forceinline__ uint32_t row16_incl_sum(uint32_t x) {
     x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);   // row_shr:1
@@ -129,65 +123,96 @@ __device__ __forceinline__ uint32_t row16_incl_sum(uint32_t x) {
     return x;
 }
 
+// Inclusive maximum over all 64 lanes: row shifts, then the row broadcasts of
+// lanes 15 and 31 carry it across rows.
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false));   // row_shr:1
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false));   // row_shr:2
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false));   // row_shr:4
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false));   // row_shr:8
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false));   // row_bcast:15
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false));   // row_bcast:31
+    return x;
+}
+
+// Set bits of mask at positions [off, off + cnt), off < 64, cnt <= 64 - off.
+__device__ __forceinline__ uint32_t bits_in(uint64_t mask, uint32_t off, uint32_t cnt) {
+    const uint64_t x = mask >> off;
+    return cnt ? (uint32_t)__popcll(x << (64u - cnt)) : 0u;
+}
+
+// A wave's LDS scratch for corank_wave.
+struct CorankLds {
+    uint64_t comp[64];   // candidate (key, lane) of every lane, read back as broadcasts
+    uint32_t head[64];   // level tag | run + 1 at the lane where a run's candidates start
+};
+
 // Returns c_k in lane k (k < Kg <= 16); other lanes return 0.  All 64 lanes
-// call.  Resolution h = 2^l is handled with shifts.
-__device__ uint64_t corank_wave(const uint32_t* __restrict__ keys, uint64_t gb, uint64_t glen, uint64_t L,
-                                uint32_t Kg, uint64_t r, uint32_t flip, int lane) {
-    const bool own = (uint32_t)lane < Kg;
-    const uint64_t nk = own ? min(L, glen - (uint64_t)lane * L) : 0;
+// call with the same arguments; positions inside a run are below 2^32.
+//
+// The candidates of a level sit in lanes run by run (run k's in lanes off_k ..
+// off_k + cnt_k - 1, in block order), so lane order is (run, block) order and
+// the stable order of candidates is (key, lane).  A lane finds its run from
+// the heads the runs write into LDS (prefix maximum over the lanes; tags grow
+// with the level, so stale heads of earlier levels lose), ranks its candidate
+// against all others read back from LDS as broadcasts, and the runs count
+// their inside candidates from two ballots.  The sum of the lower bounds is
+// kept as a scalar, so the bounds on t_h need no reduction.
+__device__ uint32_t corank_wave(const uint32_t* __restrict__ keys, uint64_t gb, uint64_t glen, uint64_t L,
+                                uint32_t Kg, uint32_t r, uint32_t flip, int lane, CorankLds* sh) {
+    const uint32_t nk = (uint32_t)lane < Kg ? (uint32_t)min(L, glen - (uint64_t)lane * L) : 0u;
     const uint64_t maxlen = Kg > 1 ? L : glen;
-    int lh = 0;
-    while ((1ull << lh) <= maxlen) ++lh;   // first resolution 2^lh exceeds every run
-    uint32_t lo = 0, hi = 0;               // bounds on floor(c_k / 2^(l+1)), lane k
+    // first resolution 2^lh exceeds every run
+    const int lh = maxlen ? 64 - __builtin_clzll(maxlen) : 0;
+    cgu32* kp = gptr(keys) + gb;
+    sh->head[lane] = 0u;
+    uint32_t lo = 0, hi = 0;   // bounds on floor(c_k / 2^(l+1)), lane k
+    uint32_t slo = 0;          // sum of lo over the runs
     for (int l = lh - 1; l >= 0; --l) {
-        const uint32_t nb = (uint32_t)(nk >> l);   // full blocks of run k at resolution 2^l
+        const uint32_t nb = nk >> l;   // full blocks of run k at resolution 2^l
         const uint32_t jlo = 2u * lo;
         // block hi at resolution 2h is never inside (floor(c_k/2h) <= hi), so
         // its second half 2hi+1 is decided and only [2lo, 2hi] are candidates
-        const uint32_t jhi = min(2u * hi, nb == 0 ? 0u : nb - 1u);
-        const uint32_t cnt = (own && nb > jlo) ? jhi - jlo + 1u : 0u;
+        const uint32_t cnt = nb > jlo ? min(2u * hi, nb - 1u) - jlo + 1u : 0u;
         const uint32_t incl = row16_incl_sum(cnt);
         const uint32_t off = incl - cnt;
         const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 15);
-
-        // candidate owned by this lane: run kk = the last k with off_k <= lane
-        // (off is non-decreasing, so that is the number of k >= 1 with
-        // off_k <= lane); straight-line, with off_k read into scalars
-        uint32_t kk = 0;
-#pragma unroll
-        for (uint32_t k = 1; k < kMaxFanout; ++k) {
-            const uint32_t ok = (uint32_t)__builtin_amdgcn_readlane((int)off, (int)k);
-            kk += (k < Kg && ok <= (uint32_t)lane) ? 1u : 0u;
-        }
+        const uint32_t tag = (uint32_t)(lh - l) << 8;
+        if (cnt) sh->head[off] = tag | (uint32_t)(lane + 1);
+        lds_wave_sync();
+        const uint32_t kk = (wave_incl_max(sh->head[lane]) & 0xFFu) - 1u;
         const bool valid = (uint32_t)lane < total;
-        const uint32_t my_off = (uint32_t)__shfl((int)off, (int)kk, 64);
-        const uint32_t my_jlo = (uint32_t)__shfl((int)jlo, (int)kk, 64);
-        const uint32_t local = (uint32_t)lane - my_off;
+        // block index of this lane's candidate = lane + (jlo - off) of its run
+        const uint32_t d = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(kk << 2), (int)(jlo - off));
         uint64_t comp = ~0ull;
         if (valid) {
-            const uint64_t pos = ((uint64_t)(my_jlo + local + 1u) << l) - 1u;
-            const uint32_t key = keys[gb + (uint64_t)kk * L + pos] ^ flip;
-            comp = ((uint64_t)key << 32) | ((uint64_t)kk << 8) | (uint64_t)local;
+            const uint32_t pos = (((uint32_t)lane + d + 1u) << l) - 1u;
+            const uint32_t key = kp[(uint64_t)kk * L + pos] ^ flip;
+            comp = ((uint64_t)key << 32) | (uint32_t)lane;
         }
+        sh->comp[lane] = comp;
+        lds_wave_sync();
         uint32_t rank = 0;
-        for (uint32_t mu = 0; mu < total; ++mu) rank += readlane_u64(comp, mu) < comp ? 1u : 0u;
+        for (uint32_t m = 0; m < total; m += 8) {
+#pragma unroll
+            for (uint32_t e = 0; e < 8; ++e) rank += sh->comp[m + e] < comp ? 1u : 0u;
+        }
 
-        const uint32_t sum2lo = (uint32_t)__builtin_amdgcn_readlane((int)row16_incl_sum(own ? jlo : 0u), 15);
+        // t_h in [ceil((r - Kg(h-1)) / h), floor(r / h)]; all wave-uniform
         const uint64_t hm1 = (1ull << l) - 1u;
-        const int64_t num = (int64_t)r - (int64_t)Kg * (int64_t)hm1;
-        const uint64_t tlo = num > 0 ? ((uint64_t)num + hm1) >> l : 0;
-        const uint64_t thi = r >> l;
-        const uint64_t dlo = tlo > sum2lo ? tlo - sum2lo : 0u;
-        const uint64_t dhi = thi > sum2lo ? thi - sum2lo : 0u;
-        const uint32_t mlo = dlo < (uint64_t)total ? (uint32_t)dlo : total;
-        const uint32_t mhi = dhi < (uint64_t)total ? (uint32_t)dhi : total;
+        const uint64_t kh = (uint64_t)Kg * hm1;
+        const uint32_t tlo = (uint64_t)r > kh ? (uint32_t)(((uint64_t)r - kh + hm1) >> l) : 0u;
+        const uint32_t thi = r >> l;
+        const uint32_t sj = 2u * slo;   // sum of jlo
+        const uint32_t dlo = tlo > sj ? tlo - sj : 0u;
+        const uint32_t dhi = thi > sj ? thi - sj : 0u;
+        const uint32_t mlo = dlo < total ? dlo : total;
+        const uint32_t mhi = dhi < total ? dhi : total;
         const uint64_t blo = __ballot(valid && rank < mlo);
         const uint64_t bhi = __ballot(valid && rank < mhi);
-        const uint64_t mask = cnt ? (((cnt >= 64 ? ~0ull : ((1ull << cnt) - 1))) << off) : 0ull;
-        const uint32_t nlo = jlo + (uint32_t)__popcll(blo & mask);
-        const uint32_t nhi = jlo + (uint32_t)__popcll(bhi & mask);
-        lo = own ? nlo : 0u;
-        hi = own ? nhi : 0u;
+        lo = jlo + bits_in(blo, off, cnt);
+        hi = jlo + bits_in(bhi, off, cnt);
+        slo = 2u * slo + (uint32_t)__popcll(blo);
     }
     return lo;
 }
@@ -195,8 +220,10 @@ __device__ uint64_t corank_wave(const uint32_t* __restrict__ keys, uint64_t gb, 
 // One wave per tile of a merge round: the split at the tile's first output.
 // The round reads the buffer its tasks do not write.
 __global__ __launch_bounds__(256) void k_corank_tiles(Phase ph, Bufs b, RoundArgs ra, uint32_t* __restrict__ table) {
+    __shared__ CorankLds sh[4];
     const int lane = threadIdx.x & 63;
-    const uint64_t t = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint64_t t = (uint64_t)blockIdx.x * 4u + (uint64_t)wave;
     if (t >= ph.tiles) return;
     const TileRef tr = tile_ref(ph, b, t);
     const uint32_t grp = tr.local / (uint32_t)ra.tpg;
@@ -205,17 +232,19 @@ __global__ __launch_bounds__(256) void k_corank_tiles(Phase ph, Bufs b, RoundArg
     const uint64_t gb = (uint64_t)grp * span;
     const uint64_t glen = min(span, tr.n - gb);
     const uint32_t Kg = (uint32_t)((glen + ra.L - 1) / ra.L);
-    uint64_t c = 0;
-    if (i > 0) c = corank_wave(tr.src_k, gb, glen, ra.L, Kg, i * (uint64_t)ra.Tout, 0u, lane);
-    if ((uint32_t)lane < ra.K) table[t * ra.K + (uint64_t)lane] = (uint32_t)c;
+    uint32_t c = 0;
+    if (i > 0) c = corank_wave(tr.src_k, gb, glen, ra.L, Kg, (uint32_t)(i * ra.Tout), 0u, lane, &sh[wave]);
+    if ((uint32_t)lane < ra.K) table[t * ra.K + (uint64_t)lane] = c;
 }
 
 __global__ __launch_bounds__(256) void k_corank_queries(const uint32_t* __restrict__ keys, uint64_t n,
                                                         uint64_t L, uint32_t K, const uint64_t* __restrict__ qg,
                                                         const uint64_t* __restrict__ qr, uint64_t nq,
                                                         uint32_t* __restrict__ split, uint32_t flip) {
+    __shared__ CorankLds sh[4];
     const int lane = threadIdx.x & 63;
-    const uint64_t q = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint64_t q = (uint64_t)blockIdx.x * 4u + (uint64_t)wave;
     if (q >= nq) return;
     const uint64_t g = qg[q];
     const uint64_t r = qr[q];
@@ -229,8 +258,8 @@ __global__ __launch_bounds__(256) void k_corank_queries(const uint32_t* __restri
         return;
     }
     const uint32_t Kg = (uint32_t)((glen + L - 1) / L);
-    const uint64_t c = corank_wave(keys, gb, glen, L, Kg, r, flip, lane);
-    if ((uint32_t)lane < K) split[q * K + (uint64_t)lane] = (uint32_t)c;
+    const uint32_t c = corank_wave(keys, gb, glen, L, Kg, (uint32_t)r, flip, lane, &sh[wave]);
+    if ((uint32_t)lane < K) split[q * K + (uint64_t)lane] = c;
 }
 
 // ===========================================================================
