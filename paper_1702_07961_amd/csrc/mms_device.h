@@ -69,9 +69,18 @@ __device__ __forceinline__ void cex(Elem<true>& lo, Elem<true>& hi) {
     hi.k = sw ? a.k : b.k; hi.t = sw ? a.t : b.t; hi.v = sw ? a.v : b.v;
 }
 
+// Median of three unsigned values in one instruction: with c = 0 it is
+// min(a, b), with c = ~0 it is max(a, b), so a lane-dependent c picks the
+// lower or upper half of a compare-exchange without a select.
+__device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t d;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 // keep the earlier (want_first) or the later of `mine` and `other`
 __device__ __forceinline__ Elem<false> pick(const Elem<false>& mine, const Elem<false>& other, bool want_first) {
-    return {want_first ? min(mine.k, other.k) : max(mine.k, other.k)};
+    return {med3_u32(mine.k, other.k, want_first ? 0u : ~0u)};
 }
 __device__ __forceinline__ Elem<true> pick(const Elem<true>& mine, const Elem<true>& other, bool want_first) {
     bool other_first = before(other, mine);
@@ -404,11 +413,11 @@ __device__ __forceinline__ void block_sort_keys(uint32_t (&m)[EM], uint32_t* scr
         m[4 * c + 3] = v.w;
     }
     if constexpr (EM == 8) {                             // index bit 2 = lane bit 0
-        const bool hi_lane = (ul & 1u) != 0;
+        const uint32_t keep_max = (ul & 1u) ? ~0u : 0u;
 #pragma unroll
         for (int e = 0; e < EM; ++e) {
             const uint32_t o = (uint32_t)__builtin_amdgcn_mov_dpp((int)m[e], 0xB1, 0xF, 0xF, false);
-            m[e] = hi_lane ? max(m[e], o) : min(m[e], o);
+            m[e] = med3_u32(m[e], o, keep_max);
         }
     }
 #pragma unroll
