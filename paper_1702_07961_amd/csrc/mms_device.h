@@ -483,8 +483,6 @@ __device__ __forceinline__ void merge_pair_range_keys(const uint32_t* X, uint32_
     constexpr uint32_t N = (uint32_t)kWave * EM;
     uint32_t p = lds_corank2(X, aA, la, aB, lb, d0, lane);
     uint32_t q = d0 - p;
-    // last readable index of each run (any LDS word is readable when empty)
-    const uint32_t la1 = la ? la - 1u : 0u, lb1 = lb ? lb - 1u : 0u;
     for (uint32_t o = d0; o < d1; o += N) {
         uint32_t m[EM];
         uint32_t u = 0;
@@ -503,20 +501,28 @@ __device__ __forceinline__ void merge_pair_range_keys(const uint32_t* X, uint32_
                 u += (uint32_t)__popcll(__ballot(a[e] <= b[e]));
             }
         } else {
-            // near the end of a run: read a clamped index and substitute the
-            // sentinel, with no branch per element
+            // near the end of a run: the same reads, then the sentinel for
+            // every position past the run's end, with no branch per element.
+            // Those reads stay below X + (end of the last run) + N, inside
+            // the caller's LDS (the layouts keep at least N words of other
+            // LDS data after each buffer); what they return is discarded.
+            // Keys equal to the sentinel can carry p past la (they are then
+            // indistinguishable from it), so the cursors are capped first.
+            const uint32_t pc = min(p, la), qc = min(q, lb);
+            const uint32_t* Ap = X + aA + pc + (uint32_t)lane;
+            const uint32_t* Bp = X + aB + qc + (N - 1u) - (uint32_t)lane;
+            const uint32_t ra = la - pc, rb = lb - qc;   // elements left in A and B
             uint32_t a[EM], b[EM];
 #pragma unroll
             for (int e = 0; e < EM; ++e) {
-                const uint32_t k = (uint32_t)e * kWave + (uint32_t)lane;
-                a[e] = X[aA + min(p + k, la1)];
-                b[e] = X[aB + min(q + (N - 1u - k), lb1)];
+                a[e] = Ap[e * kWave];
+                b[e] = Bp[-(e * kWave)];
             }
 #pragma unroll
             for (int e = 0; e < EM; ++e) {
                 const uint32_t k = (uint32_t)e * kWave + (uint32_t)lane;
-                const uint32_t av = p + k < la ? a[e] : kSentKey;
-                const uint32_t bv = q + (N - 1u - k) < lb ? b[e] : kSentKey;
+                const uint32_t av = k < ra ? a[e] : kSentKey;
+                const uint32_t bv = N - 1u - k < rb ? b[e] : kSentKey;
                 m[e] = min(av, bv);
                 u += (uint32_t)__popcll(__ballot(av <= bv));
             }

@@ -36,6 +36,8 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort(Phase ph, Bufs b, uint32_t
     uint32_t* Yv = P ? smem + 3 * T : nullptr;
     uint32_t* seg0 = smem + (P ? 4 : 2) * T;        // [W + 1] run starts (= prefix lengths)
     uint32_t* scr = seg0 + 32;                       // keys: W wave-private transpose scratches
+    // the keys-only block merge reads up to 64*kEM1 words past Yk's last run
+    static_assert(P || 32u + W * Xpose<kEM1>::WORDS >= 64u * kEM1, "LDS after Yk is shorter than a merge block");
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform

@@ -205,6 +205,8 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
     uint32_t* bufA = smem;
     uint32_t* bufB = smem + cap;
     uint32_t* scr = smem + 2 * cap;
+    // the block merge reads up to 64*EM words past a buffer's last run
+    static_assert(W * Xpose<EM>::WORDS >= 64u * EM, "LDS after bufB is shorter than a merge block");
     uint32_t* mbase = scr + W * Xpose<EM>::WORDS;     // three piece tables of kMetaWords
     auto meta = [&](int which) {
         uint32_t* mb = mbase + kMetaWords * (uint32_t)which;

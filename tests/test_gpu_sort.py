@@ -68,6 +68,19 @@ def test_keys_extreme_values(mms):
     assert np.array_equal(host(mms.sort(dev(x), i32=True)), oracle.sort(x, i32=True))
 
 
+@pytest.mark.parametrize("n,frac", [(T, 0.5), (T * K * 3 + 5, 0.25), (300_001, 0.9), (T * K * K + 11, 0.6)])
+def test_keys_bulk_sentinel_valued(mms, n, frac):
+    """Many keys equal to the merge's sentinel (0xFFFFFFFF unsigned, INT32_MAX
+    signed): a run that ends beside a run of such keys must not let the merge
+    cursors run past it."""
+    u = mmsgen.unit_doubles(mmsgen.seed_for(9, n % 7), n)
+    x = mmsgen.uniform_u32(mmsgen.seed_for(10, n % 7), n)
+    xu = np.where(u < frac, np.uint32(0xFFFFFFFF), x).astype(np.uint32)
+    assert np.array_equal(host(mms.sort(dev(xu), i32=False)), oracle.sort(xu))
+    xs = np.where(u < frac, np.uint32(0x7FFFFFFF), x).astype(np.uint32)
+    assert np.array_equal(host(mms.sort(dev(xs), i32=True)), oracle.sort(xs, i32=True))
+
+
 @pytest.mark.parametrize("n", [1000, T * K + 3, 300_001])
 def test_keys_signed(mms, n):
     x = mmsgen.uniform_u32(mmsgen.seed_for(2, 5), n)
