@@ -155,9 +155,12 @@ int mms_segmented_sort(const uint32_t* d_kin, uint32_t* d_kout, const uint32_t* 
  * merge output tile (multiple of 256, 1024..8192), variant the merge kernel
  * shape (0: 64x16-key blocks, 8 waves; 1: 64x8-key blocks, 16 waves;
  * 2: 64x8-key blocks, 8 waves; 3: as 2 with two workgroups per compute
- * unit, for merge tiles up to about 6656).  count == 0 restores the built-in default
- * (K = 16, 8192, variant 0, overridable by MMS_FANOUT / MMS_TOUT /
- * MMS_MERGE_VARIANT).  Workspace sizes depend on the table: query
+ * unit, for merge tiles up to 7168), base the keys-only base-case shape
+ * (keys per lane x waves of one 2048-key tile: 0: 8 x 4, 1: 4 x 8,
+ * 2: 16 x 2; §4.3's base case sorts a tile per thread block).  count == 0
+ * restores the built-in default (K = 16, 8192, variant 0, base 0,
+ * overridable by MMS_FANOUT / MMS_TOUT / MMS_MERGE_VARIANT /
+ * MMS_BASE_SHAPE).  Workspace sizes depend on the table: query
  * mms_workspace_bytes after changing it.  Process-wide, thread-safe.
  */
 typedef struct {
@@ -165,6 +168,7 @@ typedef struct {
     uint32_t fanout;
     uint32_t merge_tile;
     uint32_t variant;
+    uint32_t base;
 } mms_tuning_t;
 
 int mms_set_tuning(const mms_tuning_t* entries, uint32_t count);

@@ -192,15 +192,17 @@ def segmented_sort(keys, offsets, values=None, out_keys=None, out_values=None, i
 
 
 def set_tuning(entries):
-    """Install a tuning table: iterable of (max_log2_n, fanout, merge_tile, variant)."""
+    """Install a tuning table: iterable of (max_log2_n, fanout, merge_tile,
+    variant[, base])."""
     entries = list(entries)
     arr = (_lib.MmsTuning * max(1, len(entries)))()
-    for i, (l2, k, t, v) in enumerate(entries):
-        arr[i] = _lib.MmsTuning(int(l2), int(k), int(t), int(v))
+    for i, e in enumerate(entries):
+        l2, k, t, v = e[:4]
+        arr[i] = _lib.MmsTuning(int(l2), int(k), int(t), int(v), int(e[4]) if len(e) > 4 else 0)
     _lib.check(_lib.lib().mms_set_tuning(arr, len(entries)))
 
 
 def get_tuning(n: int, pairs: bool = False):
     t = _lib.MmsTuning()
     _lib.check(_lib.lib().mms_get_tuning(int(n), MMS_PAIRS if pairs else 0, t))
-    return (t.max_log2_n, t.fanout, t.merge_tile, t.variant)
+    return (t.max_log2_n, t.fanout, t.merge_tile, t.variant, t.base)

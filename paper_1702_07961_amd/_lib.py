@@ -73,6 +73,7 @@ class MmsTuning(ctypes.Structure):
         ("fanout", ctypes.c_uint32),
         ("merge_tile", ctypes.c_uint32),
         ("variant", ctypes.c_uint32),
+        ("base", ctypes.c_uint32),
     ]
 
 
@@ -204,7 +205,8 @@ def load_tuning(lib, path: str | None = None) -> int:
         entries = json.load(f)["entries"]
     arr = (MmsTuning * max(1, len(entries)))()
     for i, e in enumerate(entries):
-        arr[i] = MmsTuning(int(e["max_log2_n"]), int(e["fanout"]), int(e["merge_tile"]), int(e["variant"]))
+        arr[i] = MmsTuning(int(e["max_log2_n"]), int(e["fanout"]), int(e["merge_tile"]), int(e["variant"]),
+                           int(e.get("base", 0)))
     if lib.mms_set_tuning(arr, len(entries)) != MMS_OK:
         raise MmsError(MMS_EINVAL, f"{path}: " + lib.mms_last_error().decode())
     return len(entries)

@@ -3,7 +3,9 @@ the number of workers per platform; here per size bucket on this GPU).
 
 For every size bucket n = 2^b it times the plain keys-only sort of n uniform
 uint32 keys under each candidate (fan-out K, merge output tile, merge kernel
-shape) with HIP events, keeps the fastest, and writes the table as JSON.
+shape) with HIP events and keeps the fastest; with those fixed it then times
+each base-case shape (keys per lane x waves of a 2048-key tile), which does
+not interact with the merge parameters, and writes the table as JSON.
 The package loads that table into the library (mms_set_tuning) the first
 time the library is used.
 
@@ -24,6 +26,7 @@ DEFAULT_TABLE = os.path.join(PKG, "tuning_mi355x.json")
 FANOUTS = [4, 8, 16]
 TILES = [2048, 4096, 6144, 7168, 8192]
 VARIANTS = [0, 1, 2, 3]
+BASES = [0, 1, 2]          # 8 x 4, 4 x 8, 16 x 2 keys per lane x waves
 
 
 def candidates(log2n: int):
@@ -75,16 +78,23 @@ def tune(min_log2: int = 8, max_log2: int = 27, reps: int = 5, log=print) -> dic
             if best is None or ms < best[0]:
                 best = (ms, K, T, v)
         ms, K, T, v = best
+        base = BASES[0]
+        for bs in BASES[1:]:
+            mms.set_tuning([(64, K, T, v, bs)])
+            ws = torch.empty(max(mms.workspace_bytes(n), 256), dtype=torch.uint8, device="cuda")
+            ms_b = time_sort(mms, torch, x, out, ws, max(reps, int(2e6 // n)))
+            if ms_b < ms:
+                ms, base = ms_b, bs
         # the fastest candidate must still sort
-        mms.set_tuning([(64, K, T, v)])
+        mms.set_tuning([(64, K, T, v, base)])
         ws = torch.empty(max(mms.workspace_bytes(n), 256), dtype=torch.uint8, device="cuda")
         mms.sort(x, out=out, i32=False, workspace=ws)
         o = out.to(torch.int64) & 0xFFFFFFFF
         if not bool((o[1:] >= o[:-1]).all()):
             raise RuntimeError(f"tuned sort of 2^{b} is not sorted")
-        entries.append({"max_log2_n": b, "fanout": K, "merge_tile": T, "variant": v,
+        entries.append({"max_log2_n": b, "fanout": K, "merge_tile": T, "variant": v, "base": base,
                         "ms": round(ms, 5), "gkeys_per_s": round(n / ms / 1e6, 3)})
-        log(f"2^{b}: K={K} Tout={T} variant={v} {ms:.4f} ms ({n / ms / 1e6:.2f} Gkeys/s)")
+        log(f"2^{b}: K={K} Tout={T} variant={v} base={base} {ms:.4f} ms ({n / ms / 1e6:.2f} Gkeys/s)")
     mms.set_tuning([])
     props = torch.cuda.get_device_properties(0)
     return {"device": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),

@@ -100,16 +100,17 @@ uint32_t ceil_log2(uint64_t n) {
 }
 
 Tune env_default() {
-    Tune t{mms::kMaxFanout, mms::kToutKeys, 0};
+    Tune t{mms::kMaxFanout, mms::kToutKeys, 0, 0};
     if (const char* s = getenv("MMS_TOUT")) t.Tout = (uint32_t)atoi(s);
     if (const char* s = getenv("MMS_MERGE_VARIANT")) t.variant = atoi(s);
+    if (const char* s = getenv("MMS_BASE_SHAPE")) t.base = atoi(s);
     if (const char* s = getenv("MMS_FANOUT")) t.K = (uint32_t)atoi(s);
     return t;
 }
 
-bool valid_tune(uint32_t K, uint32_t Tout, int variant) {
+bool valid_tune(uint32_t K, uint32_t Tout, int variant, int base) {
     return K >= 2 && K <= mms::kMaxFanout && (K & (K - 1)) == 0 && Tout >= 1024 && Tout <= mms::kToutKeys &&
-           Tout % 256 == 0 && variant >= 0 && variant <= 3;
+           Tout % 256 == 0 && variant >= 0 && variant <= 3 && base >= 0 && base < mms::kBaseShapes;
 }
 
 Tune tune_for(uint64_t n, bool pairs) {
@@ -124,10 +125,10 @@ Tune tune_for(uint64_t n, bool pairs) {
                     e = &x;
                     break;
                 }
-            t = Tune{e->fanout, e->merge_tile, (int)e->variant};
+            t = Tune{e->fanout, e->merge_tile, (int)e->variant, (int)e->base};
         }
     }
-    if (!valid_tune(t.K, t.Tout, t.variant)) t = Tune{mms::kMaxFanout, mms::kToutKeys, 0};
+    if (!valid_tune(t.K, t.Tout, t.variant, t.base)) t = Tune{mms::kMaxFanout, mms::kToutKeys, 0, 0};
     if (pairs) t.Tout = mms::kToutPairs;
     return t;
 }
@@ -153,7 +154,7 @@ int run_phases(bool pairs, const PhaseList& pl, const Bufs& b, uint32_t* table, 
     hipError_t e;
     {
         Timed tm(MMS_KERNEL_TILE_SORT, s);
-        e = launch_tile_sort(pairs, pl.base, b, flip, s);
+        e = launch_tile_sort(pairs, pl.base, b, flip, tune.base, s);
     }
     if (e != hipSuccess) return hip_fail(e, "tile sort launch");
     uint64_t L = kT1;
@@ -226,7 +227,7 @@ void tuning_floor(uint32_t& K, uint32_t& Tout) {
     Tout = std::min<uint32_t>(d.Tout, kToutPairs);
     std::lock_guard<std::mutex> g(g_tune_mu);
     for (const auto& x : g_tuning) {
-        if (!valid_tune(x.fanout, x.merge_tile, (int)x.variant)) continue;
+        if (!valid_tune(x.fanout, x.merge_tile, (int)x.variant, (int)x.base)) continue;
         K = std::min(K, x.fanout);
         Tout = std::min(Tout, x.merge_tile);
     }
@@ -555,7 +556,7 @@ int mms_plan(uint64_t n, uint32_t flags, mms_plan_t* out) {
     out->n = n;
     out->flags = flags;
     out->tile = p.T;
-    out->lanes_per_tile = mms::kW1 * 64;
+    out->lanes_per_tile = (p.pairs ? mms::kW1 : mms::base_w(p.tune.base)) * 64;
     out->fanout = p.tune.K;
     out->merge_tile = p.tune.Tout;
     out->rounds = n ? p.rounds : 0;
@@ -600,9 +601,9 @@ int mms_set_tuning(const mms_tuning_t* entries, uint32_t count) {
     if (count && !entries) return fail(MMS_EINVAL, "null tuning table");
     std::vector<mms_tuning_t> v(entries, entries + count);
     for (const auto& x : v)
-        if (!valid_tune(x.fanout, x.merge_tile, (int)x.variant))
-            return fail(MMS_EINVAL, "invalid tuning entry (fanout %u, merge_tile %u, variant %u)", x.fanout,
-                        x.merge_tile, x.variant);
+        if (!valid_tune(x.fanout, x.merge_tile, (int)x.variant, (int)x.base))
+            return fail(MMS_EINVAL, "invalid tuning entry (fanout %u, merge_tile %u, variant %u, base %u)",
+                        x.fanout, x.merge_tile, x.variant, x.base);
     std::sort(v.begin(), v.end(), [](const mms_tuning_t& a, const mms_tuning_t& b) { return a.max_log2_n < b.max_log2_n; });
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tuning = std::move(v);
@@ -616,6 +617,7 @@ int mms_get_tuning(uint64_t n, uint32_t flags, mms_tuning_t* out) {
     out->fanout = t.K;
     out->merge_tile = t.Tout;
     out->variant = (uint32_t)t.variant;
+    out->base = (uint32_t)t.base;
     return MMS_OK;
 }
 

@@ -41,6 +41,7 @@ struct Tune {
     uint32_t K;      // merge fan-out
     uint32_t Tout;   // merge output tile
     int variant;     // keys-only merge kernel shape
+    int base;        // keys-only base-case shape (elements per lane x waves)
 };
 Tune tune_for(uint64_t n, bool pairs);
 uint32_t ceil_log2(uint64_t n);

@@ -12,6 +12,11 @@ namespace mms {
 constexpr int kE1 = 8;
 constexpr int kW1 = 4;
 constexpr uint32_t kT1 = 64u * kE1 * kW1;
+// Keys-only base-case shapes, elements per lane x waves, each sorting kT1
+// keys: 0 is 8 x 4, 1 is 4 x 8, 2 is 16 x 2.  The key-value path uses kE1 x kW1.
+constexpr int kBaseShapes = 3;
+constexpr int base_e(int shape) { return shape == 1 ? 4 : shape == 2 ? 16 : 8; }
+constexpr int base_w(int shape) { return shape == 1 ? 8 : shape == 2 ? 2 : 4; }
 constexpr int kEM = 8;      // merge block of the key-value path
 constexpr int kEM1 = 8;     // merge block of the keys-only base case
 constexpr int kW3 = 8;      // waves of the key-value merge
@@ -130,7 +135,7 @@ struct RoundArgs {
     uint64_t tpg;          // tiles per full group
 };
 
-hipError_t launch_tile_sort(bool pairs, const Phase& ph, const Bufs& b, uint32_t flip, hipStream_t s);
+hipError_t launch_tile_sort(bool pairs, const Phase& ph, const Bufs& b, uint32_t flip, int base_shape, hipStream_t s);
 
 hipError_t launch_corank_tiles(const Phase& ph, const Bufs& b, const RoundArgs& ra, uint32_t* table,
                                hipStream_t s);

@@ -387,21 +387,28 @@ static hipError_t allow_lds(const void* f, size_t bytes) {
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-hipError_t launch_tile_sort(bool pairs, const Phase& ph, const Bufs& b, uint32_t flip, hipStream_t s) {
+template <int E, int W>
+static hipError_t launch_tile_sort_keys(const Phase& ph, const Bufs& b, uint32_t flip, hipStream_t s) {
+    static_assert(64u * E * W == kT1, "a base-case shape sorts kT1 keys");
+    const size_t lds = (2u * kT1 + 32u + W * Xpose<kEM1>::WORDS) * sizeof(uint32_t);
+    hipError_t e = allow_lds((const void*)k_tile_sort<E, W, false>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_tile_sort<E, W, false>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, flip);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_sort(bool pairs, const Phase& ph, const Bufs& b, uint32_t flip, int base_shape,
+                            hipStream_t s) {
     if (ph.tiles == 0) return hipSuccess;
-    if (pairs) {
-        const size_t lds = (4u * kT1 + 32u) * sizeof(uint32_t);
-        hipError_t e = allow_lds((const void*)k_tile_sort<kE1, kW1, true>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_tile_sort<kE1, kW1, true>), dim3((unsigned)ph.tiles), dim3(kW1 * 64), lds, s, ph, b,
-                           flip);
-    } else {
-        const size_t lds = (2u * kT1 + 32u + kW1 * Xpose<kEM1>::WORDS) * sizeof(uint32_t);
-        hipError_t e = allow_lds((const void*)k_tile_sort<kE1, kW1, false>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_tile_sort<kE1, kW1, false>), dim3((unsigned)ph.tiles), dim3(kW1 * 64), lds, s, ph, b,
-                           flip);
+    if (!pairs) {
+        if (base_shape == 1) return launch_tile_sort_keys<base_e(1), base_w(1)>(ph, b, flip, s);
+        if (base_shape == 2) return launch_tile_sort_keys<base_e(2), base_w(2)>(ph, b, flip, s);
+        return launch_tile_sort_keys<base_e(0), base_w(0)>(ph, b, flip, s);
     }
+    const size_t lds = (4u * kT1 + 32u) * sizeof(uint32_t);
+    hipError_t e = allow_lds((const void*)k_tile_sort<kE1, kW1, true>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_tile_sort<kE1, kW1, true>), dim3((unsigned)ph.tiles), dim3(kW1 * 64), lds, s, ph, b, flip);
     return hipGetLastError();
 }
 

@@ -68,6 +68,21 @@ def test_keys_extreme_values(mms):
     assert np.array_equal(host(mms.sort(dev(x), i32=True)), oracle.sort(x, i32=True))
 
 
+@pytest.mark.parametrize("base", [0, 1, 2])
+@pytest.mark.parametrize("n", [1, T - 1, T, T + 1, T * K * 2 + 77, 300_001])
+def test_keys_base_shapes(mms, base, n):
+    """Every keys-only base-case shape the tuner can choose (8 x 4, 4 x 8 and
+    16 x 2 keys per lane x waves) sorts, unsigned and signed."""
+    x = mmsgen.family("sixteen" if n % 2 else "uniform", mmsgen.seed_for(11, n % 13), n)
+    try:
+        mms.set_tuning([(64, K, 4096, 2, base)])
+        assert np.array_equal(host(mms.sort(dev(x), i32=False)), oracle.sort(x))
+        assert np.array_equal(host(mms.sort(dev(x), i32=True)), oracle.sort(x, i32=True))
+    finally:
+        mms.set_tuning([])
+        mms._lib.load_tuning(mms._lib.lib())
+
+
 @pytest.mark.parametrize("n,frac", [(T, 0.5), (T * K * 3 + 5, 0.25), (300_001, 0.9), (T * K * K + 11, 0.6)])
 def test_keys_bulk_sentinel_valued(mms, n, frac):
     """Many keys equal to the merge's sentinel (0xFFFFFFFF unsigned, INT32_MAX

@@ -32,7 +32,8 @@ def test_committed_tuning_table_loads():
     t = _lib.MmsTuning()
     for e in entries:
         assert lib.mms_get_tuning(1 << e["max_log2_n"], 0, t) == 0
-        assert (t.fanout, t.merge_tile, t.variant) == (e["fanout"], e["merge_tile"], e["variant"])
+        assert (t.fanout, t.merge_tile, t.variant, t.base) == (e["fanout"], e["merge_tile"], e["variant"],
+                                                               e.get("base", 0))
     # pairs keep the key-value merge tile whatever the table says
     assert lib.mms_get_tuning(1 << 27, _lib.MMS_PAIRS, t) == 0 and t.merge_tile == 4096
 
@@ -43,6 +44,7 @@ def test_autotune_candidates():
     big = set(autotune.candidates(27))
     assert len(big) == len(autotune.FANOUTS) * len(autotune.TILES) * len(autotune.VARIANTS)
     assert {v for _, _, v in big} == {0, 1, 2, 3}
+    assert autotune.BASES == [0, 1, 2]
 
 
 def test_traffic_is_null_when_sources_change(monkeypatch, tmp_path):
