@@ -23,7 +23,7 @@ import time
 PKG = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(PKG, "tuning_mi355x.json")
 
-FANOUTS = [4, 8, 16]
+FANOUTS = [2, 4, 8, 16]   # 32 would need more than 64 probe lanes in the partition
 TILES = [2048, 4096, 6144, 7168, 8192]
 VARIANTS = [0, 1, 2, 3]
 BASES = [0, 1, 2]          # 8 x 4, 4 x 8, 16 x 2 keys per lane x waves
