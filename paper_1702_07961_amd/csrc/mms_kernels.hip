@@ -152,34 +152,44 @@ struct CorankLds {
 // Returns c_k in lane k (k < Kg <= 16); other lanes return 0.  All 64 lanes
 // call with the same arguments; positions inside a run are below 2^32.
 //
-// The candidates of a level sit in lanes run by run (run k's in lanes off_k ..
+// Each round refines the resolution by 2^s: s = 1 in general, s = 2 when at
+// most 9 runs take part.  With bounds lo_k <= floor(c_k/h) <= hi_k and
+// sum(hi - lo) < K, the sub-blocks of h' = h/2^s that can still be inside
+// are [2^s lo, 2^s hi + 2^s - 2] (sub-block 2^s(hi+1) - 1 being inside would
+// put c_k past block hi), at most (2^(s+1) - 1)K - 2^s in all: 3K - 2 <= 46
+// for K <= 16, 7K - 4 <= 59 for K <= 9, one per lane either way.
+//
+// The candidates of a round sit in lanes run by run (run k's in lanes off_k ..
 // off_k + cnt_k - 1, in block order), so lane order is (run, block) order and
 // the stable order of candidates is (key, lane).  A lane finds its run from
 // the heads the runs write into LDS (prefix maximum over the lanes; tags grow
-// with the level, so stale heads of earlier levels lose), ranks its candidate
+// with the round, so stale heads of earlier rounds lose), ranks its candidate
 // against all others read back from LDS as broadcasts, and the runs count
 // their inside candidates from two ballots.  The sum of the lower bounds is
 // kept as a scalar, so the bounds on t_h need no reduction.
-__device__ uint32_t corank_wave(const uint32_t* __restrict__ keys, uint64_t gb, uint64_t glen, uint64_t L,
-                                uint32_t Kg, uint32_t r, uint32_t flip, int lane, CorankLds* sh) {
+template <int STEP>
+__device__ uint32_t corank_rounds(const uint32_t* __restrict__ keys, uint64_t gb, uint64_t glen, uint64_t L,
+                                  uint32_t Kg, uint32_t r, uint32_t flip, int lane, CorankLds* sh) {
     const uint32_t nk = (uint32_t)lane < Kg ? (uint32_t)min(L, glen - (uint64_t)lane * L) : 0u;
     const uint64_t maxlen = Kg > 1 ? L : glen;
-    // first resolution 2^lh exceeds every run
-    const int lh = maxlen ? 64 - __builtin_clzll(maxlen) : 0;
     cgu32* kp = gptr(keys) + gb;
     sh->head[lane] = 0u;
-    uint32_t lo = 0, hi = 0;   // bounds on floor(c_k / 2^(l+1)), lane k
+    // resolution 2^l with 2^l > every run: lo = hi = 0 bound floor(c_k / 2^l)
+    int l = maxlen ? 64 - __builtin_clzll(maxlen) : 0;
+    uint32_t lo = 0, hi = 0;   // lane k
     uint32_t slo = 0;          // sum of lo over the runs
-    for (int l = lh - 1; l >= 0; --l) {
+    uint32_t tag = 0;
+    while (l > 0) {
+        const int s = STEP == 1 ? 1 : min(STEP, l);
+        l -= s;
+        tag += 256u;
         const uint32_t nb = nk >> l;   // full blocks of run k at resolution 2^l
-        const uint32_t jlo = 2u * lo;
-        // block hi at resolution 2h is never inside (floor(c_k/2h) <= hi), so
-        // its second half 2hi+1 is decided and only [2lo, 2hi] are candidates
-        const uint32_t cnt = nb > jlo ? min(2u * hi, nb - 1u) - jlo + 1u : 0u;
+        const uint32_t jlo = lo << s;
+        const uint32_t jmax = (hi << s) + (1u << s) - 2u;
+        const uint32_t cnt = nb > jlo ? min(jmax, nb - 1u) - jlo + 1u : 0u;
         const uint32_t incl = row16_incl_sum(cnt);
         const uint32_t off = incl - cnt;
         const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 15);
-        const uint32_t tag = (uint32_t)(lh - l) << 8;
         if (cnt) sh->head[off] = tag | (uint32_t)(lane + 1);
         lds_wave_sync();
         const uint32_t kk = (wave_incl_max(sh->head[lane]) & 0xFFu) - 1u;
@@ -195,6 +205,8 @@ __device__ uint32_t corank_wave(const uint32_t* __restrict__ keys, uint64_t gb, 
         sh->comp[lane] = comp;
         lds_wave_sync();
         uint32_t rank = 0;
+        // two trips' reads in flight: at most 64 VGPRs, eight waves per SIMD
+#pragma unroll 2
         for (uint32_t m = 0; m < total; m += 8) {
 #pragma unroll
             for (uint32_t e = 0; e < 8; ++e) rank += sh->comp[m + e] < comp ? 1u : 0u;
@@ -205,7 +217,7 @@ __device__ uint32_t corank_wave(const uint32_t* __restrict__ keys, uint64_t gb, 
         const uint64_t kh = (uint64_t)Kg * hm1;
         const uint32_t tlo = (uint64_t)r > kh ? (uint32_t)(((uint64_t)r - kh + hm1) >> l) : 0u;
         const uint32_t thi = r >> l;
-        const uint32_t sj = 2u * slo;   // sum of jlo
+        const uint32_t sj = slo << s;   // sum of jlo
         const uint32_t dlo = tlo > sj ? tlo - sj : 0u;
         const uint32_t dhi = thi > sj ? thi - sj : 0u;
         const uint32_t mlo = dlo < total ? dlo : total;
@@ -214,9 +226,15 @@ __device__ uint32_t corank_wave(const uint32_t* __restrict__ keys, uint64_t gb, 
         const uint64_t bhi = __ballot(valid && rank < mhi);
         lo = jlo + bits_in(blo, off, cnt);
         hi = jlo + bits_in(bhi, off, cnt);
-        slo = 2u * slo + (uint32_t)__popcll(blo);
+        slo = sj + (uint32_t)__popcll(blo);
     }
     return lo;
+}
+
+__device__ uint32_t corank_wave(const uint32_t* __restrict__ keys, uint64_t gb, uint64_t glen, uint64_t L,
+                                uint32_t Kg, uint32_t r, uint32_t flip, int lane, CorankLds* sh) {
+    if (Kg <= 9) return corank_rounds<2>(keys, gb, glen, L, Kg, r, flip, lane, sh);
+    return corank_rounds<1>(keys, gb, glen, L, Kg, r, flip, lane, sh);
 }
 
 // One wave per tile of a merge round: the split at the tile's first output.
