@@ -534,72 +534,6 @@ __device__ __forceinline__ void merge_pair_range_keys(const uint32_t* X, uint32_
     }
 }
 
-// One merge level over segments with 4-aligned starts: level-lvl segment i
-// starts at sbeg[i<<lvl] and holds plen[(i+1)<<lvl] - plen[i<<lvl] keys
-// (indices clamped to nseg0).  Waves split the physical range [0,
-// sbeg[nseg0]) at multiples of 4.
-//
-// Waves are shared out between the level's pairs in proportion to the
-// pairs' sizes: wave w belongs to the pair holding the midpoint of its
-// equal share of the level, and a pair's waves split it evenly, so a wave
-// normally merges one contiguous range with one split search.  A pair that
-// holds no midpoint goes to the wave whose share contains its start.
-template <int EM, class Sink>
-__device__ __forceinline__ void merge_level_keys(const uint32_t* X, const uint32_t* sbeg, const uint32_t* plen,
-                                                 uint32_t nseg0, uint32_t lvl, const Sink& out, uint32_t* scr,
-                                                 int wave, int nwaves, int lane) {
-    // all quantities below stay under 2^22, the range of udiv_small
-    const uint32_t total = plen[nseg0];               // keys in the level (gaps excluded)
-    const uint32_t nseg = (nseg0 + (1u << lvl) - 1u) >> lvl;
-    const uint32_t npairs = (nseg + 1u) / 2u;
-    const uint32_t W = (uint32_t)nwaves;
-    const uint32_t w = (uint32_t)wave;
-    if (total == 0) return;
-    // lane i describes pair i (npairs <= 32); the wave then walks the pairs
-    // with wave-uniform copies of those values
-    uint32_t p_aA = 0, p_aB = 0, p_la = 0, p_lb = 0, p_v0 = 0, p_v1 = 0, p_own = 0;
-    if ((uint32_t)lane < npairs) {
-        const uint32_t i = (uint32_t)lane;
-        const uint32_t g0 = min((2u * i) << lvl, nseg0);
-        const uint32_t g1 = min((2u * i + 1u) << lvl, nseg0);
-        const uint32_t g2 = min((2u * i + 2u) << lvl, nseg0);
-        p_aA = sbeg[g0];
-        p_aB = sbeg[g1];
-        p_la = plen[g1] - plen[g0];
-        p_lb = plen[g2] - plen[g1];
-        // waves whose midpoint (2v+1)*total/(2W) lies in the pair: v in [v0, v1),
-        // v0 = smallest v with (2v+1)*total >= 2*W*plen[g0]
-        const uint32_t n0 = 2u * W * plen[g0], n1 = 2u * W * plen[g2];
-        p_v0 = min(n0 <= total ? 0u : udiv_small(n0 + total - 1u, 2u * total), W);
-        p_v1 = min(n1 <= total ? 0u : udiv_small(n1 + total - 1u, 2u * total), W);
-        // no midpoint inside: the wave whose equal share holds the pair start
-        p_own = min(udiv_small(plen[g0] * W, total), W - 1u);
-    }
-    for (uint32_t i = 0; i < npairs; ++i) {
-        const uint32_t la = (uint32_t)__builtin_amdgcn_readlane((int)p_la, (int)i);
-        const uint32_t lb = (uint32_t)__builtin_amdgcn_readlane((int)p_lb, (int)i);
-        const uint32_t s = la + lb;
-        if (s == 0) continue;
-        const uint32_t v0 = (uint32_t)__builtin_amdgcn_readlane((int)p_v0, (int)i);
-        const uint32_t v1 = (uint32_t)__builtin_amdgcn_readlane((int)p_v1, (int)i);
-        uint32_t d0, d1;
-        if (v1 > v0) {
-            if (w < v0 || w >= v1) continue;
-            const uint32_t nw = v1 - v0, j = w - v0;
-            d0 = udiv_small(s * j, nw) & ~3u;
-            d1 = j + 1 == nw ? s : udiv_small(s * (j + 1), nw) & ~3u;
-        } else {
-            if (w != (uint32_t)__builtin_amdgcn_readlane((int)p_own, (int)i)) continue;
-            d0 = 0;
-            d1 = s;
-        }
-        if (d0 >= d1) continue;
-        const uint32_t aA = (uint32_t)__builtin_amdgcn_readlane((int)p_aA, (int)i);
-        const uint32_t aB = (uint32_t)__builtin_amdgcn_readlane((int)p_aB, (int)i);
-        merge_pair_range_keys<EM>(X, aA, la, aB, lb, d0, d1, out, aA, scr, lane);
-    }
-}
-
 // One merge level planned in advance: word 0 of (lvl, wave) holds the
 // wave's main range (pair index in bits 0..3, outputs [d0, d1) in bits
 // 4..17 and 18..31), word 1 a mask of further pairs the wave merges whole.

@@ -18,7 +18,6 @@ constexpr int kBaseShapes = 3;
 constexpr int base_e(int shape) { return shape == 1 ? 4 : shape == 2 ? 16 : 8; }
 constexpr int base_w(int shape) { return shape == 1 ? 8 : shape == 2 ? 2 : 4; }
 constexpr int kEM = 8;      // merge block of the key-value path
-constexpr int kEM1 = 8;     // merge block of the keys-only base case
 constexpr int kW3 = 8;      // waves of the key-value merge
 constexpr uint32_t kToutKeys = 8192;   // largest keys-only merge tile
 constexpr uint32_t kToutPairs = 4096;

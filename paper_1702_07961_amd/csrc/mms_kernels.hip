@@ -18,26 +18,24 @@
 namespace mms {
 
 // ===========================================================================
-// Base case: one workgroup of W1 waves sorts T1 = 64*E1*W1 elements.
-// Each wave loads a contiguous chunk of 64*E1 (coalesced, striped over the
-// lanes), sorts it in registers, and parks it in LDS; the W1 sorted chunks are
-// then merged level by level inside LDS, the last level straight to memory.
-// Missing elements of a ragged last tile are sentinels, which sort last and
-// are never stored.
+// Base case (§4.3), key-value pairs: one workgroup of W waves sorts
+// T = 64*E*W elements.  Each wave loads a contiguous chunk of 64*E
+// (coalesced, striped over the lanes), sorts it in registers carrying
+// (key, tag, value) with tag = tile position (stable order), and parks it in
+// LDS; the W sorted chunks are then merged level by level inside LDS, the last
+// level straight to memory.  Missing elements of a ragged last tile are
+// sentinels, which sort last and are never stored.
 // ===========================================================================
-template <int E, int W, bool P>
-__global__ __launch_bounds__(W * 64) void k_tile_sort(Phase ph, Bufs b, uint32_t flip) {
+template <int E, int W>
+__global__ __launch_bounds__(W * 64) void k_tile_sort_pairs(Phase ph, Bufs b, uint32_t flip) {
     constexpr uint32_t CH = 64u * E;
     constexpr uint32_t T = CH * W;
     extern __shared__ __align__(16) uint32_t smem[];
     uint32_t* Xk = smem;
     uint32_t* Yk = smem + T;
-    uint32_t* Xv = P ? smem + 2 * T : nullptr;
-    uint32_t* Yv = P ? smem + 3 * T : nullptr;
-    uint32_t* seg0 = smem + (P ? 4 : 2) * T;        // [W + 1] run starts (= prefix lengths)
-    uint32_t* scr = seg0 + 32;                       // keys: W wave-private transpose scratches
-    // the keys-only block merge reads up to 64*kEM1 words past Yk's last run
-    static_assert(P || 32u + W * Xpose<kEM1>::WORDS >= 64u * kEM1, "LDS after Yk is shorter than a merge block");
+    uint32_t* Xv = smem + 2 * T;
+    uint32_t* Yv = smem + 3 * T;
+    uint32_t* seg0 = smem + 4 * T;                   // [W + 1] run starts (= prefix lengths)
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
@@ -45,56 +43,156 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort(Phase ph, Bufs b, uint32_t
     const uint64_t base = (uint64_t)tr.local * T;
     const uint32_t cnt = (uint32_t)min<uint64_t>(T, tr.n - base);
     const uint32_t* in_k = tr.in_k + base;
-    const uint32_t* in_v = P ? tr.in_v + base : nullptr;
+    const uint32_t* in_v = tr.in_v + base;
     uint32_t* out_k = tr.dst_k + base;
-    uint32_t* out_v = P ? tr.dst_v + base : nullptr;
+    uint32_t* out_v = tr.dst_v + base;
     const uint32_t flip_out = tr.final_pass ? flip : 0u;
 
-    Elem<P> r[E];
+    Elem<true> r[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t j = (uint32_t)wave * CH + (uint32_t)e * 64u + (uint32_t)lane;
-        if (j < cnt) {
-            if constexpr (P) r[e] = Elem<P>{gptr(in_k)[j] ^ flip, j, gptr(in_v)[j]};
-            else r[e] = Elem<P>{gptr(in_k)[j] ^ flip};
-        } else {
-            r[e] = Elem<P>::sentinel();
-        }
+        r[e] = j < cnt ? Elem<true>{gptr(in_k)[j] ^ flip, j, gptr(in_v)[j]} : Elem<true>::sentinel();
     }
-    wave_sort_blocked<E, P>(r, lane);
+    wave_sort_blocked<E, true>(r, lane);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t idx = (uint32_t)wave * CH + (uint32_t)lane * E + (uint32_t)e;
         Xk[idx] = r[e].k;
-        if constexpr (P) Xv[idx] = r[e].v;
+        Xv[idx] = r[e].v;
     }
     if (threadIdx.x <= (unsigned)W) seg0[threadIdx.x] = threadIdx.x * CH;
     lds_barrier();
 
-    uint32_t* wscr = scr + (uint32_t)wave * Xpose<kEM1>::WORDS;
-    const bool vec = ((uintptr_t)out_k & 15u) == 0;
     for (uint32_t lvl = 0; (1u << lvl) < (uint32_t)W; ++lvl) {
-        const bool last = (2u << lvl) >= (uint32_t)W;
-        if constexpr (P) {
-            if (last) {
-                GlobalSinkLim<P> out{out_k, out_v, flip_out, cnt};
-                merge_level<kEM, P>(Xk, Xv, seg0, W, lvl, T, out, wave, W, lane);
-            } else {
-                LdsSink<P> out{Yk, Yv};
-                merge_level<kEM, P>(Xk, Xv, seg0, W, lvl, T, out, wave, W, lane);
-            }
+        if ((2u << lvl) >= (uint32_t)W) {
+            GlobalSinkLim<true> out{out_k, out_v, flip_out, cnt};
+            merge_level<kEM, true>(Xk, Xv, seg0, W, lvl, T, out, wave, W, lane);
         } else {
-            if (last) {
-                GlobalSinkKeys out{out_k, flip_out, cnt, vec};
-                merge_level_keys<kEM1>(Xk, seg0, seg0, W, lvl, out, wscr, wave, W, lane);
-            } else {
-                LdsSinkKeys out{Yk};
-                merge_level_keys<kEM1>(Xk, seg0, seg0, W, lvl, out, wscr, wave, W, lane);
-            }
+            LdsSink<true> out{Yk, Yv};
+            merge_level<kEM, true>(Xk, Xv, seg0, W, lvl, T, out, wave, W, lane);
         }
         lds_barrier();
         uint32_t* t = Xk; Xk = Yk; Yk = t;
         t = Xv; Xv = Yv; Yv = t;
+    }
+}
+
+// ===========================================================================
+// Keys-only base case: the W sorted wave chunks are merged by bitonic merges
+// across waves instead of LDS block merges.  At level lvl (runs of 2^lvl
+// chunks) the first stage compares every key with its mirror in the paired
+// run (wave w ^ (2^(lvl+1) - 1), lane 63 - l, register E - 1 - e), the next
+// stages compare at wave distances 2^(lvl-1) .. 1, each through LDS, and the
+// remaining stages (lane distances 32 .. 1, then register distances) run in
+// the wave as in its own sort.  Exchanges alternate between two LDS buffers,
+// so one barrier separates them.  A lane's E keys sit in LDS as E/4 16-byte
+// chunks whose order rotates with the lane, so the 16 lanes of a 128-bit
+// access touch 64 distinct banks.
+// ===========================================================================
+template <int E>
+__device__ __forceinline__ uint32_t chunk_word(uint32_t lane, uint32_t c) {
+    constexpr uint32_t Q = E / 4;
+    if constexpr (Q == 1) {
+        return lane * 4u;
+    } else {
+        constexpr uint32_t SH = Q == 2 ? 3u : 2u;   // lanes 2^SH apart share banks
+        return lane * (uint32_t)E + 4u * (c ^ ((lane >> SH) & (Q - 1u)));
+    }
+}
+
+template <int E>
+__device__ __forceinline__ void wave_merge_tail(Elem<false> (&r)[E], int lane) {
+#pragma unroll
+    for (int dl = kWave / 2; dl >= 1; dl >>= 1) {
+        const bool lo = (lane & dl) == 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) r[e] = pick(r[e], shfl_xor(r[e], dl), lo);
+    }
+#pragma unroll
+    for (int d = E / 2; d >= 1; d >>= 1) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if ((e & d) == 0) cex(r[e], r[e | d]);
+    }
+}
+
+template <int E, int W>
+__global__ __launch_bounds__(W * 64) void k_tile_sort_keys(Phase ph, Bufs b, uint32_t flip) {
+    constexpr uint32_t CH = 64u * E;
+    constexpr uint32_t T = CH * W;
+    constexpr uint32_t Q = E / 4;
+    static_assert(E % 4 == 0 && E <= 16, "E/4 chunks of four keys, at most four");
+    extern __shared__ __align__(16) uint32_t smem[];   // two exchange buffers of T words
+
+    const int lane = threadIdx.x & 63;
+    const uint32_t ul = (uint32_t)lane;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
+    const TileRef tr = tile_ref(ph, b, blockIdx.x);
+    const uint64_t base = (uint64_t)tr.local * T;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(T, tr.n - base);
+    const uint32_t* in_k = tr.in_k + base;
+    uint32_t* out_k = tr.dst_k + base;
+    const uint32_t flip_out = tr.final_pass ? flip : 0u;
+
+    Elem<false> r[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t j = (uint32_t)wave * CH + (uint32_t)e * 64u + ul;
+        r[e] = j < cnt ? Elem<false>{gptr(in_k)[j] ^ flip} : Elem<false>::sentinel();
+    }
+    wave_sort_blocked<E, false>(r, lane);
+
+    uint32_t buf = 0;
+    // keep the minimum (keep = 0) or the maximum (~0) of each key and the
+    // partner wave's key at the same (mirror: mirrored) position
+    auto exchange = [&](int pw, bool mirror, uint32_t keep) {
+        uint32_t* X = smem + buf * T;
+        buf ^= 1u;
+        uint32_t* mine = X + (uint32_t)wave * CH;
+#pragma unroll
+        for (uint32_t c = 0; c < Q; ++c)
+            *reinterpret_cast<uint4*>(mine + chunk_word<E>(ul, c)) =
+                make_uint4(r[4 * c].k, r[4 * c + 1].k, r[4 * c + 2].k, r[4 * c + 3].k);
+        lds_barrier();
+        const uint32_t* theirs = X + (uint32_t)pw * CH;
+#pragma unroll
+        for (uint32_t c = 0; c < Q; ++c) {
+            uint32_t o[4];
+            if (mirror) {
+                const uint4 v = *reinterpret_cast<const uint4*>(theirs + chunk_word<E>(63u - ul, Q - 1u - c));
+                o[0] = v.w; o[1] = v.z; o[2] = v.y; o[3] = v.x;
+            } else {
+                const uint4 v = *reinterpret_cast<const uint4*>(theirs + chunk_word<E>(ul, c));
+                o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) r[4 * c + j].k = med3_u32(r[4 * c + j].k, o[j], keep);
+        }
+    };
+#pragma unroll
+    for (int lvl = 0; (1 << lvl) < W; ++lvl) {
+        const int gw = 1 << lvl;
+        exchange(wave ^ (2 * gw - 1), true, (wave & gw) ? ~0u : 0u);
+#pragma unroll
+        for (int dw = gw >> 1; dw >= 1; dw >>= 1) exchange(wave ^ dw, false, (wave & dw) ? ~0u : 0u);
+        wave_merge_tail<E>(r, lane);
+    }
+
+    // wave w, lane l holds tile positions w*CH + l*E .. + E-1
+    const bool vec = ((uintptr_t)out_k & 15u) == 0;
+    gu32* g = gptr(out_k);
+#pragma unroll
+    for (uint32_t c = 0; c < Q; ++c) {
+        const uint32_t pos = (uint32_t)wave * CH + ul * (uint32_t)E + 4u * c;
+        if (vec && pos + 4u <= cnt) {
+            *reinterpret_cast<gu32x4*>(g + pos) = u32x4{r[4 * c].k ^ flip_out, r[4 * c + 1].k ^ flip_out,
+                                                        r[4 * c + 2].k ^ flip_out, r[4 * c + 3].k ^ flip_out};
+        } else {
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j)
+                if (pos + j < cnt) g[pos + j] = r[4 * c + j].k ^ flip_out;
+        }
     }
 }
 
@@ -408,10 +506,10 @@ static hipError_t allow_lds(const void* f, size_t bytes) {
 template <int E, int W>
 static hipError_t launch_tile_sort_keys(const Phase& ph, const Bufs& b, uint32_t flip, hipStream_t s) {
     static_assert(64u * E * W == kT1, "a base-case shape sorts kT1 keys");
-    const size_t lds = (2u * kT1 + 32u + W * Xpose<kEM1>::WORDS) * sizeof(uint32_t);
-    hipError_t e = allow_lds((const void*)k_tile_sort<E, W, false>, lds);
+    const size_t lds = 2u * kT1 * sizeof(uint32_t);
+    hipError_t e = allow_lds((const void*)k_tile_sort_keys<E, W>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_tile_sort<E, W, false>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, flip);
+    hipLaunchKernelGGL((k_tile_sort_keys<E, W>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, flip);
     return hipGetLastError();
 }
 
@@ -424,9 +522,9 @@ hipError_t launch_tile_sort(bool pairs, const Phase& ph, const Bufs& b, uint32_t
         return launch_tile_sort_keys<base_e(0), base_w(0)>(ph, b, flip, s);
     }
     const size_t lds = (4u * kT1 + 32u) * sizeof(uint32_t);
-    hipError_t e = allow_lds((const void*)k_tile_sort<kE1, kW1, true>, lds);
+    hipError_t e = allow_lds((const void*)k_tile_sort_pairs<kE1, kW1>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_tile_sort<kE1, kW1, true>), dim3((unsigned)ph.tiles), dim3(kW1 * 64), lds, s, ph, b, flip);
+    hipLaunchKernelGGL((k_tile_sort_pairs<kE1, kW1>), dim3((unsigned)ph.tiles), dim3(kW1 * 64), lds, s, ph, b, flip);
     return hipGetLastError();
 }
 

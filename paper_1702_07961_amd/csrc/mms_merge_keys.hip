@@ -4,7 +4,7 @@
 // of a round.  A tile's input is the K pieces of its group's runs bounded by
 // the split indices of its first and last output (§4.1).  The pieces are
 // placed at 4-aligned offsets of LDS buffer X and merged pairwise, level by
-// level, with the conflict-free block step of merge_level_keys (log2 K
+// level, with the conflict-free block step of merge_pair_range_keys (log2 K
 // levels: X->Y->X->...); the last level stores straight to memory.
 //
 // Memory latency is hidden by a three-stage pipeline: as tile t starts, the
