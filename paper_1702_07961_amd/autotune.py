@@ -4,8 +4,8 @@ the number of workers per platform; here per size bucket on this GPU).
 For every size bucket n = 2^b it times the plain keys-only sort of n uniform
 uint32 keys under each candidate (fan-out K, merge output tile, merge kernel
 shape) with HIP events and keeps the fastest; with those fixed it then times
-each base-case shape (keys per lane x waves of a 2048-key tile), which does
-not interact with the merge parameters, and writes the table as JSON.
+each base-case shape (keys per lane x waves, and with it the base tile of
+2048, 4096 or 8192 keys), and writes the table as JSON.
 The package loads that table into the library (mms_set_tuning) the first
 time the library is used.
 
@@ -26,7 +26,8 @@ DEFAULT_TABLE = os.path.join(PKG, "tuning_mi355x.json")
 FANOUTS = [2, 4, 8, 16]   # 32 would need more than 64 probe lanes in the partition
 TILES = [2048, 4096, 6144, 7168, 8192]
 VARIANTS = [0, 1, 2, 3]
-BASES = [0, 1, 2]          # 8 x 4, 4 x 8, 16 x 2 keys per lane x waves
+# keys per lane x waves: 8x4, 4x8, 16x2 (2048-key tiles), 8x8, 16x4 (4096), 8x16, 16x8 (8192)
+BASES = [0, 1, 2, 3, 4, 5, 6]
 
 
 def candidates(log2n: int):

@@ -129,7 +129,10 @@ Tune tune_for(uint64_t n, bool pairs) {
         }
     }
     if (!valid_tune(t.K, t.Tout, t.variant, t.base)) t = Tune{mms::kMaxFanout, mms::kToutKeys, 0, 0};
-    if (pairs) t.Tout = mms::kToutPairs;
+    if (pairs) {
+        t.Tout = mms::kToutPairs;
+        t.base = 0;   // the key-value base case has one shape
+    }
     return t;
 }
 
@@ -157,7 +160,7 @@ int run_phases(bool pairs, const PhaseList& pl, const Bufs& b, uint32_t* table, 
         e = launch_tile_sort(pairs, pl.base, b, flip, tune.base, s);
     }
     if (e != hipSuccess) return hip_fail(e, "tile sort launch");
-    uint64_t L = kT1;
+    uint64_t L = base_tile(tune.base);
     for (size_t r = 0; r < pl.rounds.size(); ++r, L *= tune.K) {
         const Phase& ph = pl.rounds[r];
         if (ph.tiles == 0) continue;
@@ -185,7 +188,7 @@ void build_batch_tasks(const uint64_t* seg_n, uint64_t ns, bool pairs, const Tun
     bt.phases.assign(1, {});
     bt.max_round_tiles = 0;
     bt.ntasks = 0;
-    const uint32_t T = kT1, K = tune.K;
+    const uint32_t T = base_tile(tune.base), K = tune.K;
     for (uint64_t s = 0; s < ns; ++s) {
         const uint64_t n = seg_n[s];
         if (n == 0) continue;
@@ -209,7 +212,8 @@ void build_batch_tasks(const uint64_t* seg_n, uint64_t ns, bool pairs, const Tun
 // A segment of n elements has at most n/T + 1 base tiles; round r has at
 // most n/Tout + n/(T*K) + 1 tiles (one per Tout outputs plus one per group,
 // groups <= n/(K*L) + 1 with L >= T); it has at most rounds_for(n, T, K)
-// rounds.
+// rounds.  Every base-case shape's tile is at least kT1, so the bounds taken
+// at T = kT1 hold for all of them.
 uint64_t batch_tasks_bound(uint64_t total, uint64_t ns, uint64_t maxn, uint32_t K, uint32_t Tout) {
     const uint64_t round = total / Tout + total / ((uint64_t)kT1 * K) + ns + 1;
     return total / kT1 + ns + 1 + (uint64_t)rounds_for(maxn, kT1, K) * round;
@@ -235,10 +239,11 @@ void tuning_floor(uint32_t& K, uint32_t& Tout) {
 
 void add_segment_tiles(uint64_t n, const Tune& tune, std::vector<uint64_t>& per_phase) {
     if (n == 0) return;
-    const uint32_t R = rounds_for(n, kT1, tune.K);
+    const uint32_t T = base_tile(tune.base);
+    const uint32_t R = rounds_for(n, T, tune.K);
     if (per_phase.size() < (size_t)R + 1) per_phase.resize(R + 1, 0);
-    per_phase[0] += (n + kT1 - 1) / kT1;
-    uint64_t L = kT1;
+    per_phase[0] += (n + T - 1) / T;
+    uint64_t L = T;
     for (uint32_t r = 0; r < R; ++r, L *= tune.K) per_phase[1 + r] += round_geom(n, L, tune.K, tune.Tout).tiles;
 }
 
@@ -285,8 +290,8 @@ Plan make_plan(uint64_t n, uint32_t flags) {
     Plan p{};
     p.n = n;
     p.pairs = (flags & MMS_PAIRS) != 0;
-    p.T = mms::kT1;
     p.tune = tune_for(n, p.pairs);
+    p.T = mms::base_tile(p.tune.base);
     p.rounds = rounds_for(n, p.T, p.tune.K);
     p.max_tiles = 0;
     uint64_t L = p.T;

@@ -505,8 +505,7 @@ static hipError_t allow_lds(const void* f, size_t bytes) {
 
 template <int E, int W>
 static hipError_t launch_tile_sort_keys(const Phase& ph, const Bufs& b, uint32_t flip, hipStream_t s) {
-    static_assert(64u * E * W == kT1, "a base-case shape sorts kT1 keys");
-    const size_t lds = 2u * kT1 * sizeof(uint32_t);
+    const size_t lds = 2u * 64u * E * W * sizeof(uint32_t);
     hipError_t e = allow_lds((const void*)k_tile_sort_keys<E, W>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_tile_sort_keys<E, W>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, flip);
@@ -519,6 +518,10 @@ hipError_t launch_tile_sort(bool pairs, const Phase& ph, const Bufs& b, uint32_t
     if (!pairs) {
         if (base_shape == 1) return launch_tile_sort_keys<base_e(1), base_w(1)>(ph, b, flip, s);
         if (base_shape == 2) return launch_tile_sort_keys<base_e(2), base_w(2)>(ph, b, flip, s);
+        if (base_shape == 3) return launch_tile_sort_keys<base_e(3), base_w(3)>(ph, b, flip, s);
+        if (base_shape == 4) return launch_tile_sort_keys<base_e(4), base_w(4)>(ph, b, flip, s);
+        if (base_shape == 5) return launch_tile_sort_keys<base_e(5), base_w(5)>(ph, b, flip, s);
+        if (base_shape == 6) return launch_tile_sort_keys<base_e(6), base_w(6)>(ph, b, flip, s);
         return launch_tile_sort_keys<base_e(0), base_w(0)>(ph, b, flip, s);
     }
     const size_t lds = (4u * kT1 + 32u) * sizeof(uint32_t);

@@ -182,7 +182,7 @@ def test_tuning_table(lib):
     assert p.fanout == 8 and p.rounds == expected_rounds(1 << 18, 2048, 8)
     bad = (_lib.MmsTuning * 1)(_lib.MmsTuning(20, 3, 4096, 0))
     assert lib.mms_set_tuning(bad, 1) == _lib.MMS_EINVAL
-    bad = (_lib.MmsTuning * 1)(_lib.MmsTuning(20, 8, 4096, 0, 3))     # no base-case shape 3
+    bad = (_lib.MmsTuning * 1)(_lib.MmsTuning(20, 8, 4096, 0, 7))     # no base-case shape 7
     assert lib.mms_set_tuning(bad, 1) == _lib.MMS_EINVAL
     shaped = (_lib.MmsTuning * 1)(_lib.MmsTuning(32, 8, 4096, 1, 2))
     assert lib.mms_set_tuning(shaped, 1) == 0
@@ -190,5 +190,12 @@ def test_tuning_table(lib):
     p = _lib.MmsPlan()
     assert lib.mms_plan(1 << 20, 0, p) == 0 and p.lanes_per_tile == 128      # 16 keys x 2 waves
     assert lib.mms_plan(1 << 20, _lib.MMS_PAIRS, p) == 0 and p.lanes_per_tile == 256
+    big = (_lib.MmsTuning * 1)(_lib.MmsTuning(32, 16, 7168, 3, 4))      # 8 x 16: 8192-key tiles
+    assert lib.mms_set_tuning(big, 1) == 0
+    assert lib.mms_plan(10**8, 0, p) == 0
+    assert (p.tile, p.lanes_per_tile, p.rounds) == (8192, 1024, 4)       # 12208 runs: 16^3 < 12208
+    assert lib.mms_plan(8192, 0, p) == 0 and p.rounds == 0
+    assert lib.mms_plan(8193, 0, p) == 0 and p.rounds == 1
+    assert lib.mms_plan(10**8, _lib.MMS_PAIRS, p) == 0 and p.tile == 2048
     assert lib.mms_set_tuning(None, 0) == 0
     assert lib.mms_get_tuning(10**8, 0, t) == 0 and (t.fanout, t.merge_tile, t.variant) == default

@@ -68,11 +68,12 @@ def test_keys_extreme_values(mms):
     assert np.array_equal(host(mms.sort(dev(x), i32=True)), oracle.sort(x, i32=True))
 
 
-@pytest.mark.parametrize("base", [0, 1, 2])
-@pytest.mark.parametrize("n", [1, T - 1, T, T + 1, T * K * 2 + 77, 300_001])
+@pytest.mark.parametrize("base", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("n", [1, T - 1, T, T + 1, 4 * T - 1, 4 * T + 1, T * K * 2 + 77, 300_001])
 def test_keys_base_shapes(mms, base, n):
-    """Every keys-only base-case shape the tuner can choose (8 x 4, 4 x 8 and
-    16 x 2 keys per lane x waves) sorts, unsigned and signed."""
+    """Every keys-only base-case shape the tuner can choose (8 x 4, 4 x 8,
+    16 x 2 keys per lane x waves on 2048-key tiles, 8 x 8 and 16 x 4 on 4096,
+    8 x 16 and 16 x 8 on 8192) sorts, unsigned and signed."""
     x = mmsgen.family("sixteen" if n % 2 else "uniform", mmsgen.seed_for(11, n % 13), n)
     try:
         mms.set_tuning([(64, K, 4096, 2, base)])

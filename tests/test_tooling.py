@@ -44,7 +44,7 @@ def test_autotune_candidates():
     big = set(autotune.candidates(27))
     assert len(big) == len(autotune.FANOUTS) * len(autotune.TILES) * len(autotune.VARIANTS)
     assert {v for _, _, v in big} == {0, 1, 2, 3}
-    assert autotune.BASES == [0, 1, 2]
+    assert autotune.BASES == [0, 1, 2, 3, 4, 5, 6]
 
 
 def test_traffic_is_null_when_sources_change(monkeypatch, tmp_path):
