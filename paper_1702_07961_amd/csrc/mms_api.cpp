@@ -136,6 +136,17 @@ Tune tune_for(uint64_t n, bool pairs) {
     return t;
 }
 
+// A batch of ns segments holding `total` elements has the parallel work of a
+// sort of `total` elements, so it takes that size's launch parameters; its
+// base tile stays within the mean segment (a larger tile would mostly sort
+// sentinels), else the 2048-key shape.
+Tune tune_for_batch(uint64_t total, uint64_t ns, bool pairs) {
+    Tune t = tune_for(std::max<uint64_t>(total, 1), pairs);
+    const uint64_t mean = ns ? total / ns : total;
+    if (mms::base_tile(t.base) > std::max<uint64_t>(mms::kT1, mean)) t.base = 0;
+    return t;
+}
+
 // One resident workgroup per compute unit for the persistent merge kernel.
 unsigned persistent_grid() {
     int dev = 0;
@@ -393,7 +404,8 @@ int make_seg_plan(const uint64_t* off, uint64_t ns, uint32_t flags, SegPlan& sp)
         }
     }
     if (maxn >= (1ull << 32)) return fail(MMS_EINVAL, "a segment holds 2^32 or more elements");
-    build_batch_tasks(sp.seg_n.data(), sp.seg_n.size(), sp.pairs, tune_for(maxn ? maxn : 1, sp.pairs), sp.bt);
+    build_batch_tasks(sp.seg_n.data(), sp.seg_n.size(), sp.pairs, tune_for_batch(sp.total, sp.seg_n.size(), sp.pairs),
+                      sp.bt);
     sp.off_vals = align_up(sp.total * 4);
     sp.off_table = sp.off_vals + (sp.pairs ? align_up(sp.total * 4) : 0);
     sp.ws_bytes = sp.off_table + sp.bt.table_bytes();

@@ -44,6 +44,7 @@ struct Tune {
     int base;        // keys-only base-case shape (elements per lane x waves)
 };
 Tune tune_for(uint64_t n, bool pairs);
+Tune tune_for_batch(uint64_t total, uint64_t ns, bool pairs);
 uint32_t ceil_log2(uint64_t n);
 
 constexpr uint64_t kAlign = 256;

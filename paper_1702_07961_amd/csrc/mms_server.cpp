@@ -271,19 +271,23 @@ uint64_t meta_bytes(uint64_t segs, uint64_t ntasks, uint64_t max_round_tiles, ui
 
 // The next batch: the oldest admitted request and, in admission order, every
 // later one of the same kind within the batch limits and the metadata slot.
-// The batch is planned with the tuning of its largest candidate.
+// The batch is planned with the tuning of the candidates' total (capped by
+// the batch limits), as a segmented sort of them would be.
 Batch form_batch(mms_server* s, int stream, int slot) {
     Batch b;
     b.id = s->next_batch++;
     b.stream = stream;
     b.slot = slot;
     const uint32_t kind = s->reqs[s->admitted.front()].r.flags;
-    uint64_t maxn = 0;
+    uint64_t cand_keys = 0, cand_n = 0;
     for (uint64_t t : s->admitted) {
         const Req& q = s->reqs[t];
-        if (q.r.flags == kind) maxn = std::max(maxn, q.r.n);
+        if (q.r.flags != kind || cand_n >= s->cfg.max_batch_requests) continue;
+        if (cand_n && cand_keys + q.r.n > s->cfg.max_batch_keys) continue;
+        cand_keys += q.r.n;
+        ++cand_n;
     }
-    b.tune = tune_for(maxn, (kind & MMS_PAIRS) != 0);
+    b.tune = tune_for_batch(cand_keys, cand_n, (kind & MMS_PAIRS) != 0);
     uint64_t keys = 0, ntasks = 0;
     std::vector<uint64_t> phases, mine;
     std::deque<uint64_t> rest;
