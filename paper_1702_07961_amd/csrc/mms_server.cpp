@@ -193,8 +193,10 @@ hipEvent_t take_event(mms_server* s) {
         s->event_pool.pop_back();
         return e;
     }
+    // Blocking sync: a completion thread sleeps in hipEventSynchronize rather
+    // than spinning on a core the submitting threads need.
     hipEvent_t e = nullptr;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventBlockingSync) != hipSuccess) return nullptr;
     return e;
 }
 
