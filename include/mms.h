@@ -159,7 +159,8 @@ int mms_segmented_sort(const uint32_t* d_kin, uint32_t* d_kout, const uint32_t* 
  * (keys per lane x waves, §4.3's base case sorting one tile per workgroup:
  * 0: 8 x 4, 1: 4 x 8, 2: 16 x 2, all 2048-key tiles; 3: 8 x 8 and
  * 5: 16 x 4, 4096-key tiles; 4: 8 x 16 and 6: 16 x 8, 8192-key tiles;
- * key-value sorts always use shape 0).  count == 0
+ * key-value sorts use shape 3 for shape 4, the entry's shape for 0 and 3,
+ * else shape 0).  count == 0
  * restores the built-in default (K = 16, 8192, variant 0, base 0,
  * overridable by MMS_FANOUT / MMS_TOUT / MMS_MERGE_VARIANT /
  * MMS_BASE_SHAPE).  Workspace sizes depend on the table: query

@@ -131,7 +131,10 @@ Tune tune_for(uint64_t n, bool pairs) {
     if (!valid_tune(t.K, t.Tout, t.variant, t.base)) t = Tune{mms::kMaxFanout, mms::kToutKeys, 0, 0};
     if (pairs) {
         t.Tout = mms::kToutPairs;
-        t.base = 0;   // the key-value base case has one shape
+        // key-value base cases: 8 per lane x 4 or 8 waves (8 x 16 sorts pairs
+        // slower than 8 x 8: its LDS holds one workgroup per CU)
+        if (t.base == 4) t.base = 3;
+        else if (mms::base_e(t.base) != 8) t.base = 0;
     }
     return t;
 }
@@ -573,7 +576,7 @@ int mms_plan(uint64_t n, uint32_t flags, mms_plan_t* out) {
     out->n = n;
     out->flags = flags;
     out->tile = p.T;
-    out->lanes_per_tile = (p.pairs ? mms::kW1 : mms::base_w(p.tune.base)) * 64;
+    out->lanes_per_tile = mms::base_w(p.tune.base) * 64;
     out->fanout = p.tune.K;
     out->merge_tile = p.tune.Tout;
     out->rounds = n ? p.rounds : 0;

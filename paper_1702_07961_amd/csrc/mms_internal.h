@@ -6,23 +6,20 @@
 
 namespace mms {
 
-// Compile-time kernel shapes.  The base case sorts T1 = 64*E1*W1 elements
-// per workgroup; a merge workgroup produces an output tile of Tout elements
-// with W3 waves, 64*EM elements per merge block.
-constexpr int kE1 = 8;
-constexpr int kW1 = 4;
-constexpr uint32_t kT1 = 64u * kE1 * kW1;
-// Keys-only base-case shapes, elements per lane x waves (tile = 64 E W):
-// 0: 8 x 4, 1: 4 x 8, 2: 16 x 2 (tiles of kT1 = 2048), 3: 8 x 8, 5: 16 x 4
-// (4096), 4: 8 x 16, 6: 16 x 8 (8192).  The key-value path uses kE1 x kW1,
-// shape 0's tile.
+// Compile-time kernel shapes.  The base case sorts a tile of 64*E*W elements
+// per workgroup (E per lane, W waves); a merge workgroup produces an output
+// tile of Tout elements with W3 waves, 64*EM elements per merge block.
+// Base-case shapes, E x W (tile): 0: 8 x 4, 1: 4 x 8, 2: 16 x 2 (2048),
+// 3: 8 x 8, 5: 16 x 4 (4096), 4: 8 x 16, 6: 16 x 8 (8192).  Key-value sorts
+// use shapes 0 and 3.  kT1 is the smallest tile.
 constexpr int kBaseShapes = 7;
 constexpr int kShapeE[kBaseShapes] = {8, 4, 16, 8, 8, 16, 16};
 constexpr int kShapeW[kBaseShapes] = {4, 8, 2, 8, 16, 4, 8};
 constexpr int base_e(int shape) { return kShapeE[shape]; }
 constexpr int base_w(int shape) { return kShapeW[shape]; }
 constexpr uint32_t base_tile(int shape) { return 64u * (uint32_t)base_e(shape) * (uint32_t)base_w(shape); }
-static_assert(base_tile(0) == kT1, "shape 0 is the key-value tile");
+constexpr uint32_t kT1 = 2048;
+static_assert(base_tile(0) == kT1 && base_tile(1) == kT1 && base_tile(2) == kT1, "the smallest tile");
 constexpr int kEM = 8;      // merge block of the key-value path
 constexpr int kW3 = 8;      // waves of the key-value merge
 constexpr uint32_t kToutKeys = 8192;   // largest keys-only merge tile

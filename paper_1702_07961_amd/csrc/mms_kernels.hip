@@ -18,67 +18,6 @@
 namespace mms {
 
 // ===========================================================================
-// Base case (§4.3), key-value pairs: one workgroup of W waves sorts
-// T = 64*E*W elements.  Each wave loads a contiguous chunk of 64*E
-// (coalesced, striped over the lanes), sorts it in registers carrying
-// (key, tag, value) with tag = tile position (stable order), and parks it in
-// LDS; the W sorted chunks are then merged level by level inside LDS, the last
-// level straight to memory.  Missing elements of a ragged last tile are
-// sentinels, which sort last and are never stored.
-// ===========================================================================
-template <int E, int W>
-__global__ __launch_bounds__(W * 64) void k_tile_sort_pairs(Phase ph, Bufs b, uint32_t flip) {
-    constexpr uint32_t CH = 64u * E;
-    constexpr uint32_t T = CH * W;
-    extern __shared__ __align__(16) uint32_t smem[];
-    uint32_t* Xk = smem;
-    uint32_t* Yk = smem + T;
-    uint32_t* Xv = smem + 2 * T;
-    uint32_t* Yv = smem + 3 * T;
-    uint32_t* seg0 = smem + 4 * T;                   // [W + 1] run starts (= prefix lengths)
-
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
-    const TileRef tr = tile_ref(ph, b, blockIdx.x);
-    const uint64_t base = (uint64_t)tr.local * T;
-    const uint32_t cnt = (uint32_t)min<uint64_t>(T, tr.n - base);
-    const uint32_t* in_k = tr.in_k + base;
-    const uint32_t* in_v = tr.in_v + base;
-    uint32_t* out_k = tr.dst_k + base;
-    uint32_t* out_v = tr.dst_v + base;
-    const uint32_t flip_out = tr.final_pass ? flip : 0u;
-
-    Elem<true> r[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t j = (uint32_t)wave * CH + (uint32_t)e * 64u + (uint32_t)lane;
-        r[e] = j < cnt ? Elem<true>{gptr(in_k)[j] ^ flip, j, gptr(in_v)[j]} : Elem<true>::sentinel();
-    }
-    wave_sort_blocked<E, true>(r, lane);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t idx = (uint32_t)wave * CH + (uint32_t)lane * E + (uint32_t)e;
-        Xk[idx] = r[e].k;
-        Xv[idx] = r[e].v;
-    }
-    if (threadIdx.x <= (unsigned)W) seg0[threadIdx.x] = threadIdx.x * CH;
-    lds_barrier();
-
-    for (uint32_t lvl = 0; (1u << lvl) < (uint32_t)W; ++lvl) {
-        if ((2u << lvl) >= (uint32_t)W) {
-            GlobalSinkLim<true> out{out_k, out_v, flip_out, cnt};
-            merge_level<kEM, true>(Xk, Xv, seg0, W, lvl, T, out, wave, W, lane);
-        } else {
-            LdsSink<true> out{Yk, Yv};
-            merge_level<kEM, true>(Xk, Xv, seg0, W, lvl, T, out, wave, W, lane);
-        }
-        lds_barrier();
-        uint32_t* t = Xk; Xk = Yk; Yk = t;
-        t = Xv; Xv = Yv; Yv = t;
-    }
-}
-
-// ===========================================================================
 // Keys-only base case: the W sorted wave chunks are merged by bitonic merges
 // across waves instead of LDS block merges.  At level lvl (runs of 2^lvl
 // chunks) the first stage compares every key with its mirror in the paired
@@ -101,8 +40,8 @@ __device__ __forceinline__ uint32_t chunk_word(uint32_t lane, uint32_t c) {
     }
 }
 
-template <int E>
-__device__ __forceinline__ void wave_merge_tail(Elem<false> (&r)[E], int lane) {
+template <int E, bool P>
+__device__ __forceinline__ void wave_merge_tail(Elem<P> (&r)[E], int lane) {
 #pragma unroll
     for (int dl = kWave / 2; dl >= 1; dl >>= 1) {
         const bool lo = (lane & dl) == 0;
@@ -176,7 +115,7 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort_keys(Phase ph, Bufs b, uin
         exchange(wave ^ (2 * gw - 1), true, (wave & gw) ? ~0u : 0u);
 #pragma unroll
         for (int dw = gw >> 1; dw >= 1; dw >>= 1) exchange(wave ^ dw, false, (wave & dw) ? ~0u : 0u);
-        wave_merge_tail<E>(r, lane);
+        wave_merge_tail<E, false>(r, lane);
     }
 
     // wave w, lane l holds tile positions w*CH + l*E .. + E-1
@@ -192,6 +131,114 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort_keys(Phase ph, Bufs b, uin
 #pragma unroll
             for (uint32_t j = 0; j < 4; ++j)
                 if (pos + j < cnt) g[pos + j] = r[4 * c + j].k ^ flip_out;
+        }
+    }
+}
+
+// ===========================================================================
+// Key-value base case, same scheme as the keys-only one.  Elements carry
+// (key, tag) with tag = tile position, so (key, tag) is the stable order and
+// is unique; the values are staged in LDS as loaded and gathered by tag when
+// the sorted tile is stored.  Exchanges move keys and tags as two arrays.
+// LDS: values (T words), then two exchange buffers of 2T words.
+// ===========================================================================
+template <int E, int W>
+__global__ __launch_bounds__(W * 64) void k_tile_sort_pairs(Phase ph, Bufs b, uint32_t flip) {
+    constexpr uint32_t CH = 64u * E;
+    constexpr uint32_t T = CH * W;
+    constexpr uint32_t Q = E / 4;
+    static_assert(E % 4 == 0 && E <= 16, "E/4 chunks of four elements, at most four");
+    extern __shared__ __align__(16) uint32_t smem[];
+    uint32_t* V = smem;
+
+    const int lane = threadIdx.x & 63;
+    const uint32_t ul = (uint32_t)lane;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
+    const TileRef tr = tile_ref(ph, b, blockIdx.x);
+    const uint64_t base = (uint64_t)tr.local * T;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(T, tr.n - base);
+    const uint32_t* in_k = tr.in_k + base;
+    const uint32_t* in_v = tr.in_v + base;
+    uint32_t* out_k = tr.dst_k + base;
+    uint32_t* out_v = tr.dst_v + base;
+    const uint32_t flip_out = tr.final_pass ? flip : 0u;
+
+    Elem<true> r[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t j = (uint32_t)wave * CH + (uint32_t)e * 64u + ul;
+        if (j < cnt) {
+            r[e] = Elem<true>{gptr(in_k)[j] ^ flip, j, 0u};
+            V[j] = gptr(in_v)[j];
+        } else {
+            r[e] = Elem<true>::sentinel();
+        }
+    }
+    wave_sort_blocked<E, true>(r, lane);
+
+    uint32_t buf = 0;
+    auto exchange = [&](int pw, bool mirror, bool want_first) {
+        uint32_t* Xk = smem + T + buf * 2u * T;
+        uint32_t* Xt = Xk + T;
+        buf ^= 1u;
+        const uint32_t me = (uint32_t)wave * CH;
+#pragma unroll
+        for (uint32_t c = 0; c < Q; ++c) {
+            const uint32_t w = me + chunk_word<E>(ul, c);
+            *reinterpret_cast<uint4*>(Xk + w) = make_uint4(r[4 * c].k, r[4 * c + 1].k, r[4 * c + 2].k, r[4 * c + 3].k);
+            *reinterpret_cast<uint4*>(Xt + w) = make_uint4(r[4 * c].t, r[4 * c + 1].t, r[4 * c + 2].t, r[4 * c + 3].t);
+        }
+        lds_barrier();
+        const uint32_t them = (uint32_t)pw * CH;
+#pragma unroll
+        for (uint32_t c = 0; c < Q; ++c) {
+            uint32_t ok[4], ot[4];
+            if (mirror) {
+                const uint32_t w = them + chunk_word<E>(63u - ul, Q - 1u - c);
+                const uint4 vk = *reinterpret_cast<const uint4*>(Xk + w);
+                const uint4 vt = *reinterpret_cast<const uint4*>(Xt + w);
+                ok[0] = vk.w; ok[1] = vk.z; ok[2] = vk.y; ok[3] = vk.x;
+                ot[0] = vt.w; ot[1] = vt.z; ot[2] = vt.y; ot[3] = vt.x;
+            } else {
+                const uint32_t w = them + chunk_word<E>(ul, c);
+                const uint4 vk = *reinterpret_cast<const uint4*>(Xk + w);
+                const uint4 vt = *reinterpret_cast<const uint4*>(Xt + w);
+                ok[0] = vk.x; ok[1] = vk.y; ok[2] = vk.z; ok[3] = vk.w;
+                ot[0] = vt.x; ot[1] = vt.y; ot[2] = vt.z; ot[3] = vt.w;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) r[4 * c + j] = pick(r[4 * c + j], Elem<true>{ok[j], ot[j], 0u}, want_first);
+        }
+    };
+#pragma unroll
+    for (int lvl = 0; (1 << lvl) < W; ++lvl) {
+        const int gw = 1 << lvl;
+        exchange(wave ^ (2 * gw - 1), true, (wave & gw) == 0);
+#pragma unroll
+        for (int dw = gw >> 1; dw >= 1; dw >>= 1) exchange(wave ^ dw, false, (wave & dw) == 0);
+        wave_merge_tail<E, true>(r, lane);
+    }
+
+    // wave w, lane l holds tile positions w*CH + l*E .. + E-1; values by tag
+    const bool vec = (((uintptr_t)out_k | (uintptr_t)out_v) & 15u) == 0;
+    gu32* gk = gptr(out_k);
+    gu32* gv = gptr(out_v);
+#pragma unroll
+    for (uint32_t c = 0; c < Q; ++c) {
+        const uint32_t pos = (uint32_t)wave * CH + ul * (uint32_t)E + 4u * c;
+        if (vec && pos + 4u <= cnt) {
+            *reinterpret_cast<gu32x4*>(gk + pos) = u32x4{r[4 * c].k ^ flip_out, r[4 * c + 1].k ^ flip_out,
+                                                         r[4 * c + 2].k ^ flip_out, r[4 * c + 3].k ^ flip_out};
+            *reinterpret_cast<gu32x4*>(gv + pos) =
+                u32x4{V[r[4 * c].t], V[r[4 * c + 1].t], V[r[4 * c + 2].t], V[r[4 * c + 3].t]};
+        } else {
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                if (pos + j < cnt) {
+                    gk[pos + j] = r[4 * c + j].k ^ flip_out;
+                    gv[pos + j] = V[r[4 * c + j].t];
+                }
+            }
         }
     }
 }
@@ -512,6 +559,15 @@ static hipError_t launch_tile_sort_keys(const Phase& ph, const Bufs& b, uint32_t
     return hipGetLastError();
 }
 
+template <int E, int W>
+static hipError_t launch_tile_sort_pairs(const Phase& ph, const Bufs& b, uint32_t flip, hipStream_t s) {
+    const size_t lds = 5u * 64u * E * W * sizeof(uint32_t);
+    hipError_t e = allow_lds((const void*)k_tile_sort_pairs<E, W>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_tile_sort_pairs<E, W>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, flip);
+    return hipGetLastError();
+}
+
 hipError_t launch_tile_sort(bool pairs, const Phase& ph, const Bufs& b, uint32_t flip, int base_shape,
                             hipStream_t s) {
     if (ph.tiles == 0) return hipSuccess;
@@ -524,11 +580,9 @@ hipError_t launch_tile_sort(bool pairs, const Phase& ph, const Bufs& b, uint32_t
         if (base_shape == 6) return launch_tile_sort_keys<base_e(6), base_w(6)>(ph, b, flip, s);
         return launch_tile_sort_keys<base_e(0), base_w(0)>(ph, b, flip, s);
     }
-    const size_t lds = (4u * kT1 + 32u) * sizeof(uint32_t);
-    hipError_t e = allow_lds((const void*)k_tile_sort_pairs<kE1, kW1>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_tile_sort_pairs<kE1, kW1>), dim3((unsigned)ph.tiles), dim3(kW1 * 64), lds, s, ph, b, flip);
-    return hipGetLastError();
+    if (base_shape == 3) return launch_tile_sort_pairs<base_e(3), base_w(3)>(ph, b, flip, s);
+    if (base_shape == 4) return launch_tile_sort_pairs<base_e(4), base_w(4)>(ph, b, flip, s);
+    return launch_tile_sort_pairs<base_e(0), base_w(0)>(ph, b, flip, s);
 }
 
 hipError_t launch_corank_tiles(const Phase& ph, const Bufs& b, const RoundArgs& ra, uint32_t* table, hipStream_t s) {

@@ -196,6 +196,10 @@ def test_tuning_table(lib):
     assert (p.tile, p.lanes_per_tile, p.rounds) == (8192, 1024, 4)       # 12208 runs: 16^3 < 12208
     assert lib.mms_plan(8192, 0, p) == 0 and p.rounds == 0
     assert lib.mms_plan(8193, 0, p) == 0 and p.rounds == 1
-    assert lib.mms_plan(10**8, _lib.MMS_PAIRS, p) == 0 and p.tile == 2048
+    assert lib.mms_plan(10**8, _lib.MMS_PAIRS, p) == 0 and (p.tile, p.lanes_per_tile) == (4096, 512)   # 8 x 8
+    wide = (_lib.MmsTuning * 1)(_lib.MmsTuning(32, 16, 7168, 3, 6))     # 16 x 8: keys only
+    assert lib.mms_set_tuning(wide, 1) == 0
+    assert lib.mms_plan(10**8, 0, p) == 0 and p.tile == 8192
+    assert lib.mms_plan(10**8, _lib.MMS_PAIRS, p) == 0 and (p.tile, p.lanes_per_tile) == (2048, 256)
     assert lib.mms_set_tuning(None, 0) == 0
     assert lib.mms_get_tuning(10**8, 0, t) == 0 and (t.fanout, t.merge_tile, t.variant) == default

@@ -79,6 +79,11 @@ def test_keys_base_shapes(mms, base, n):
         mms.set_tuning([(64, K, 4096, 2, base)])
         assert np.array_equal(host(mms.sort(dev(x), i32=False)), oracle.sort(x))
         assert np.array_equal(host(mms.sort(dev(x), i32=True)), oracle.sort(x, i32=True))
+        # key-value sorts map the shape to 8 x 4 or 8 x 8
+        v = np.arange(n, dtype=np.uint32)[::-1].copy()
+        gk, gv = mms.sort_pairs(dev(x), dev(v), i32=True)
+        ok, ov = oracle.sort(x, v, i32=True)
+        assert np.array_equal(host(gk), ok) and np.array_equal(host(gv), ov)
     finally:
         mms.set_tuning([])
         mms._lib.load_tuning(mms._lib.lib())
