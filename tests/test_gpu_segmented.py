@@ -133,3 +133,26 @@ def test_segmented_batch_workload_sampled(mms):
     for s in rng.choice(4096, 24, replace=False):
         a, b = int(off[s]), int(off[s + 1])
         assert np.array_equal(got[a:b], oracle.sort(x[a:b])), s
+
+
+@pytest.mark.parametrize("base", [0, 3, 4, 6])
+def test_segmented_base_tiles(mms, base):
+    """Batches under every base tile (2048, 4096, 8192 keys): many small
+    segments (the batch caps its base tile at the mean segment) and a mix
+    around the larger tiles; keys and stable pairs."""
+    small = [0, 1, 3, 100, 257, 999, 2048, 2049] * 40
+    mixed = [4095, 4096, 4097, 8191, 8192, 8193, 3 * 8192 + 5, 16 * 8192 + 1, 70_001]
+    try:
+        mms.set_tuning([(64, K, 4096, 3, base)])
+        for sizes in (small, mixed, small + mixed):
+            off = offsets_of(sizes)
+            x = mmsgen.sixteen_u32(mmsgen.seed_for(4, 5 + base), int(off[-1]))
+            got = host(mms.segmented_sort(dev(x), off, i32=True))
+            assert np.array_equal(got, oracle.sort_segments(x, off, i32=True))
+            v = np.arange(x.size, dtype=np.uint32)
+            gk, gv = mms.segmented_sort(dev(x), off, values=dev(v), i32=False)
+            ok, ov = oracle.sort_segments(x, off, vals=v)
+            assert np.array_equal(host(gk), ok) and np.array_equal(host(gv), ov)
+    finally:
+        mms.set_tuning([])
+        mms._lib.load_tuning(mms._lib.lib())
