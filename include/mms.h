@@ -149,8 +149,10 @@ int mms_segmented_sort(const uint32_t* d_kin, uint32_t* d_kout, const uint32_t* 
 
 /*
  * Tuning table (written by the autotuner; §6.2 tunes K and the number of
- * workers per platform).  A sort whose largest array has n elements uses the
- * first entry with ceil(log2 n) <= max_log2_n, else the last entry.  fanout
+ * workers per platform).  A sort of n elements uses the first entry with
+ * ceil(log2 n) <= max_log2_n, else the last entry; a batched sort of
+ * num_segs segments holding n elements in all uses the entry for n, with
+ * its base tile capped at max(2048, n / num_segs) (shape 0 otherwise).  fanout
  * is the merge fan-out K (power of two, 2..16), merge_tile the keys-only
  * merge output tile (multiple of 256, 1024..8192), variant the merge kernel
  * shape (0: 64x16-key blocks, 8 waves; 1: 64x8-key blocks, 16 waves;
