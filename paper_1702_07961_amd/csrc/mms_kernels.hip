@@ -481,27 +481,54 @@ __global__ __launch_bounds__(W * 64) void k_merge_pairs(Phase ph, Bufs b, RoundA
         }
         return;
     }
-    if (threadIdx.x < Kg) {
-        const uint32_t k = threadIdx.x;
-        const uint64_t nk = min(L, glen - (uint64_t)k * L);
-        // the clamps only guard memory safety; exact splits never trigger them
-        const uint32_t s = i == 0 ? 0u : min(table[t * K + k], (uint32_t)nk);
-        const uint32_t e = (obeg + Tout >= glen) ? (uint32_t)nk : min(table[(t + 1) * K + k], (uint32_t)nk);
-        start[k] = s;
-        seg0[k + 1] = e > s ? e - s : 0u;
+    if (wave == 0) {   // lane k < Kg: piece k; piece starts by a row prefix sum
+        uint32_t len = 0;
+        if ((uint32_t)lane < Kg) {
+            const uint32_t k = (uint32_t)lane;
+            const uint64_t nk = min(L, glen - (uint64_t)k * L);
+            // the clamps only guard memory safety; exact splits never trigger them
+            const uint32_t s = i == 0 ? 0u : min(table[t * K + k], (uint32_t)nk);
+            const uint32_t e = (obeg + Tout >= glen) ? (uint32_t)nk : min(table[(t + 1) * K + k], (uint32_t)nk);
+            start[k] = s;
+            len = e > s ? e - s : 0u;
+        }
+        const uint32_t incl = row16_incl_sum(len);
+        if ((uint32_t)lane < Kg) seg0[lane + 1] = min(incl, cnt);
+        if (lane == 0) seg0[0] = 0;
     }
     lds_barrier();
-    if (threadIdx.x == 0) {
-        seg0[0] = 0;
-        for (uint32_t k = 0; k < Kg; ++k) seg0[k + 1] = min(seg0[k + 1] + seg0[k], cnt);
-    }
-    lds_barrier();
-    for (uint32_t k = 0; k < Kg; ++k) {
-        const uint32_t dst0 = seg0[k], len = seg0[k + 1] - dst0;
-        const uint64_t src0 = gb + (uint64_t)k * L + start[k];
-        for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) {
-            Xk[dst0 + j] = gptr(src_k)[src0 + j];
-            Xv[dst0 + j] = gptr(src_v)[src0 + j];
+    // every thread issues the loads of all its slots of the concatenated
+    // pieces at once (slot j lies in the last piece k with seg0[k] <= j),
+    // then parks them in LDS
+    {
+        constexpr uint32_t NT = W * 64u;
+        constexpr int PER = (int)((kToutPairs + NT - 1u) / NT);
+        const uint32_t filled = seg0[Kg];
+        uint32_t lk[PER], lv[PER];
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const uint32_t j = (uint32_t)r * NT + threadIdx.x;
+            lk[r] = 0u;
+            lv[r] = 0u;
+            if (j < filled) {
+                uint32_t lo = 0, hi = Kg;
+                while (hi - lo > 1u) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (seg0[mid] <= j) lo = mid;
+                    else hi = mid;
+                }
+                const uint64_t src = gb + (uint64_t)lo * L + start[lo] + (j - seg0[lo]);
+                lk[r] = gptr(src_k)[src];
+                lv[r] = gptr(src_v)[src];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const uint32_t j = (uint32_t)r * NT + threadIdx.x;
+            if (j < filled) {
+                Xk[j] = lk[r];
+                Xv[j] = lv[r];
+            }
         }
     }
     lds_barrier();
@@ -610,6 +637,7 @@ hipError_t launch_corank_queries(const uint32_t* keys, uint64_t n, uint64_t L, u
 hipError_t launch_merge_pairs(const Phase& ph, const Bufs& b, const RoundArgs& ra, const uint32_t* table,
                               uint32_t flip, hipStream_t s) {
     if (ph.tiles == 0) return hipSuccess;
+    if (ra.Tout > kToutPairs) return hipErrorInvalidValue;   // the loader covers kToutPairs slots
     const size_t lds = (4u * ra.Tout + 2u * kMaxFanout + 8u) * sizeof(uint32_t);
     hipError_t e = allow_lds((const void*)k_merge_pairs<kW3>, lds);
     if (e != hipSuccess) return e;
