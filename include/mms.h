@@ -149,24 +149,31 @@ int mms_segmented_sort(const uint32_t* d_kin, uint32_t* d_kout, const uint32_t* 
 
 /*
  * Tuning table (written by the autotuner; §6.2 tunes K and the number of
- * workers per platform).  A sort of n elements uses the first entry with
- * ceil(log2 n) <= max_log2_n, else the last entry; a batched sort of
- * num_segs segments holding n elements in all uses the entry for n, with
- * its base tile capped at max(2048, n / num_segs) (shape 0 otherwise).  fanout
- * is the merge fan-out K (power of two, 2..16), merge_tile the keys-only
- * merge output tile (multiple of 256, 1024..8192), variant the merge kernel
- * shape (0: 64x16-key blocks, 8 waves; 1: 64x8-key blocks, 16 waves;
- * 2: 64x8-key blocks, 8 waves; 3: as 2 with two workgroups per compute
- * unit, for merge tiles up to 7168), base the keys-only base-case shape
- * (keys per lane x waves, §4.3's base case sorting one tile per workgroup:
- * 0: 8 x 4, 1: 4 x 8, 2: 16 x 2, all 2048-key tiles; 3: 8 x 8 and
- * 5: 16 x 4, 4096-key tiles; 4: 8 x 16 and 6: 16 x 8, 8192-key tiles;
- * key-value sorts use shape 3 for shape 4, the entry's shape for 0 and 3,
- * else shape 0).  count == 0
- * restores the built-in default (K = 16, 8192, variant 0, base 0,
+ * workers per platform).  Entries are of one of two kinds, flags 0 for
+ * keys-only sorts and MMS_PAIRS for key-value sorts; a kind with no entries
+ * uses the keys-only ones.  A sort of n elements uses the first entry of its
+ * kind with ceil(log2 n) <= max_log2_n, else the last one; a batched sort of
+ * num_segs segments holding n elements in all uses the entry for n, with its
+ * base tile capped at max(2048, n / num_segs) (shape 0 otherwise).
+ *   fanout      merge fan-out K (power of two, 2..16)
+ *   merge_tile  keys-only merge output tile (multiple of 256, 1024..8192;
+ *               key-value merges use 4096 whatever the entry says)
+ *   variant     keys-only merge kernel shape (0: 64x16-key blocks, 8 waves;
+ *               1: 64x8-key blocks, 16 waves; 2: 64x8-key blocks, 8 waves;
+ *               3: as 2 with two workgroups per compute unit, for merge tiles
+ *               up to 7168)
+ *   base        base-case shape, keys per lane x waves (§4.3's base case
+ *               sorts one tile per workgroup): 0: 8 x 4, 1: 4 x 8, 2: 16 x 2,
+ *               all 2048-key tiles; 3: 8 x 8 and 5: 16 x 4, 4096-key tiles;
+ *               4: 8 x 16 and 6: 16 x 8, 8192-key tiles.  Key-value sorts
+ *               use shape 3 for shape 4, shapes 0 and 3 as given, else 0.
+ *   flags       0 or MMS_PAIRS, the kind
+ * count == 0 restores the built-in default (K = 16, 8192, variant 0, base 0,
  * overridable by MMS_FANOUT / MMS_TOUT / MMS_MERGE_VARIANT /
  * MMS_BASE_SHAPE).  Workspace sizes depend on the table: query
- * mms_workspace_bytes after changing it.  Process-wide, thread-safe.
+ * mms_workspace_bytes after changing it.  mms_get_tuning reports the
+ * parameters a sort of n elements of the kind `flags` selects.
+ * Process-wide, thread-safe.
  */
 typedef struct {
     uint32_t max_log2_n;
@@ -174,6 +181,7 @@ typedef struct {
     uint32_t merge_tile;
     uint32_t variant;
     uint32_t base;
+    uint32_t flags;
 } mms_tuning_t;
 
 int mms_set_tuning(const mms_tuning_t* entries, uint32_t count);

@@ -193,12 +193,13 @@ def segmented_sort(keys, offsets, values=None, out_keys=None, out_values=None, i
 
 def set_tuning(entries):
     """Install a tuning table: iterable of (max_log2_n, fanout, merge_tile,
-    variant[, base])."""
+    variant[, base[, flags]]), flags MMS_PAIRS for key-value entries."""
     entries = list(entries)
     arr = (_lib.MmsTuning * max(1, len(entries)))()
     for i, e in enumerate(entries):
         l2, k, t, v = e[:4]
-        arr[i] = _lib.MmsTuning(int(l2), int(k), int(t), int(v), int(e[4]) if len(e) > 4 else 0)
+        arr[i] = _lib.MmsTuning(int(l2), int(k), int(t), int(v), int(e[4]) if len(e) > 4 else 0,
+                                int(e[5]) if len(e) > 5 else 0)
     _lib.check(_lib.lib().mms_set_tuning(arr, len(entries)))
 
 

@@ -74,6 +74,7 @@ class MmsTuning(ctypes.Structure):
         ("merge_tile", ctypes.c_uint32),
         ("variant", ctypes.c_uint32),
         ("base", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
     ]
 
 
@@ -202,11 +203,12 @@ def load_tuning(lib, path: str | None = None) -> int:
     if not path or not os.path.exists(path):
         return 0
     with open(path) as f:
-        entries = json.load(f)["entries"]
+        table = json.load(f)
+    entries = [(e, 0) for e in table["entries"]] + [(e, MMS_PAIRS) for e in table.get("pairs_entries", [])]
     arr = (MmsTuning * max(1, len(entries)))()
-    for i, e in enumerate(entries):
+    for i, (e, kind) in enumerate(entries):
         arr[i] = MmsTuning(int(e["max_log2_n"]), int(e["fanout"]), int(e["merge_tile"]), int(e["variant"]),
-                           int(e.get("base", 0)))
+                           int(e.get("base", 0)), kind)
     if lib.mms_set_tuning(arr, len(entries)) != MMS_OK:
         raise MmsError(MMS_EINVAL, f"{path}: " + lib.mms_last_error().decode())
     return len(entries)

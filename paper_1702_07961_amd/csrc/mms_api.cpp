@@ -113,20 +113,25 @@ bool valid_tune(uint32_t K, uint32_t Tout, int variant, int base) {
            Tout % 256 == 0 && variant >= 0 && variant <= 3 && base >= 0 && base < mms::kBaseShapes;
 }
 
+// Entries of one kind (keys-only or key-value) ordered by max_log2_n; a sort
+// takes the first with ceil(log2 n) <= max_log2_n, else the last.  Key-value
+// sorts use the keys-only entries when the table has none of their own.
 Tune tune_for(uint64_t n, bool pairs) {
     Tune t = env_default();
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
-        if (!g_tuning.empty()) {
-            const uint32_t l = ceil_log2(n);
-            const mms_tuning_t* e = &g_tuning.back();
-            for (const auto& x : g_tuning)
-                if (l <= x.max_log2_n) {
-                    e = &x;
-                    break;
-                }
-            t = Tune{e->fanout, e->merge_tile, (int)e->variant, (int)e->base};
+        const uint32_t want = pairs ? MMS_PAIRS : 0u;
+        bool any = false;
+        for (const auto& x : g_tuning) any = any || (x.flags & MMS_PAIRS) == want;
+        const uint32_t kind = any ? want : 0u;
+        const uint32_t l = ceil_log2(n);
+        const mms_tuning_t* e = nullptr;
+        for (const auto& x : g_tuning) {
+            if ((x.flags & MMS_PAIRS) != kind) continue;
+            e = &x;
+            if (l <= x.max_log2_n) break;
         }
+        if (e) t = Tune{e->fanout, e->merge_tile, (int)e->variant, (int)e->base};
     }
     if (!valid_tune(t.K, t.Tout, t.variant, t.base)) t = Tune{mms::kMaxFanout, mms::kToutKeys, 0, 0};
     if (pairs) {
@@ -247,7 +252,7 @@ void tuning_floor(uint32_t& K, uint32_t& Tout) {
     for (const auto& x : g_tuning) {
         if (!valid_tune(x.fanout, x.merge_tile, (int)x.variant, (int)x.base)) continue;
         K = std::min(K, x.fanout);
-        Tout = std::min(Tout, x.merge_tile);
+        if (!(x.flags & MMS_PAIRS)) Tout = std::min(Tout, x.merge_tile);   // key-value merges use kToutPairs
     }
 }
 
@@ -620,11 +625,15 @@ int mms_segmented_sort(const uint32_t* d_kin, uint32_t* d_kout, const uint32_t* 
 int mms_set_tuning(const mms_tuning_t* entries, uint32_t count) {
     if (count && !entries) return fail(MMS_EINVAL, "null tuning table");
     std::vector<mms_tuning_t> v(entries, entries + count);
-    for (const auto& x : v)
+    for (const auto& x : v) {
         if (!valid_tune(x.fanout, x.merge_tile, (int)x.variant, (int)x.base))
             return fail(MMS_EINVAL, "invalid tuning entry (fanout %u, merge_tile %u, variant %u, base %u)",
                         x.fanout, x.merge_tile, x.variant, x.base);
-    std::sort(v.begin(), v.end(), [](const mms_tuning_t& a, const mms_tuning_t& b) { return a.max_log2_n < b.max_log2_n; });
+        if (x.flags & ~MMS_PAIRS) return fail(MMS_EINVAL, "tuning entry flags 0x%x", x.flags);
+    }
+    std::stable_sort(v.begin(), v.end(), [](const mms_tuning_t& a, const mms_tuning_t& b) {
+        return a.max_log2_n < b.max_log2_n;
+    });
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tuning = std::move(v);
     return MMS_OK;
@@ -638,6 +647,7 @@ int mms_get_tuning(uint64_t n, uint32_t flags, mms_tuning_t* out) {
     out->merge_tile = t.Tout;
     out->variant = (uint32_t)t.variant;
     out->base = (uint32_t)t.base;
+    out->flags = flags & MMS_PAIRS;
     return MMS_OK;
 }
 

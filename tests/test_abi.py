@@ -197,6 +197,16 @@ def test_tuning_table(lib):
     assert lib.mms_plan(8192, 0, p) == 0 and p.rounds == 0
     assert lib.mms_plan(8193, 0, p) == 0 and p.rounds == 1
     assert lib.mms_plan(10**8, _lib.MMS_PAIRS, p) == 0 and (p.tile, p.lanes_per_tile) == (4096, 512)   # 8 x 8
+    kinds = (_lib.MmsTuning * 3)(_lib.MmsTuning(32, 16, 7168, 3, 4, 0),
+                                 _lib.MmsTuning(20, 4, 4096, 0, 0, _lib.MMS_PAIRS),
+                                 _lib.MmsTuning(32, 8, 4096, 0, 3, _lib.MMS_PAIRS))
+    assert lib.mms_set_tuning(kinds, 3) == 0                              # entries of both kinds
+    assert lib.mms_get_tuning(10**8, 0, t) == 0 and (t.fanout, t.base, t.flags) == (16, 4, 0)
+    assert lib.mms_get_tuning(1 << 18, _lib.MMS_PAIRS, t) == 0 and (t.fanout, t.base) == (4, 0)
+    assert lib.mms_get_tuning(10**8, _lib.MMS_PAIRS, t) == 0 and (t.fanout, t.base, t.flags) == (8, 3, 1)
+    assert lib.mms_plan(10**8, _lib.MMS_PAIRS, p) == 0 and (p.fanout, p.tile) == (8, 4096)
+    bad = (_lib.MmsTuning * 1)(_lib.MmsTuning(32, 16, 7168, 3, 4, 2))   # unknown kind flag
+    assert lib.mms_set_tuning(bad, 1) == _lib.MMS_EINVAL
     wide = (_lib.MmsTuning * 1)(_lib.MmsTuning(32, 16, 7168, 3, 6))     # 16 x 8: keys only
     assert lib.mms_set_tuning(wide, 1) == 0
     assert lib.mms_plan(10**8, 0, p) == 0 and p.tile == 8192

@@ -89,6 +89,25 @@ def test_keys_base_shapes(mms, base, n):
         mms._lib.load_tuning(mms._lib.lib())
 
 
+@pytest.mark.parametrize("pk,pbase", [(4, 0), (8, 3), (2, 3)])
+def test_pairs_own_tuning_entries(mms, pk, pbase):
+    """Key-value sorts follow their own tuning entries while keys-only sorts
+    keep theirs; both stay exact."""
+    n = T * 16 * 3 + 77
+    x = mmsgen.sixteen_u32(mmsgen.seed_for(12, pk), n)
+    v = np.arange(n, dtype=np.uint32)
+    try:
+        mms.set_tuning([(64, 16, 7168, 3, 4, 0), (64, pk, 4096, 0, pbase, mms.MMS_PAIRS)])
+        assert mms.get_tuning(n, pairs=True)[1] == pk and mms.get_tuning(n)[1] == 16
+        gk, gv = mms.sort_pairs(dev(x), dev(v), i32=False)
+        ok, ov = oracle.sort(x, v)
+        assert np.array_equal(host(gk), ok) and np.array_equal(host(gv), ov)
+        assert np.array_equal(host(mms.sort(dev(x), i32=False)), oracle.sort(x))
+    finally:
+        mms.set_tuning([])
+        mms._lib.load_tuning(mms._lib.lib())
+
+
 @pytest.mark.parametrize("n,frac", [(T, 0.5), (T * K * 3 + 5, 0.25), (300_001, 0.9), (T * K * K + 11, 0.6)])
 def test_keys_bulk_sentinel_valued(mms, n, frac):
     """Many keys equal to the merge's sentinel (0xFFFFFFFF unsigned, INT32_MAX

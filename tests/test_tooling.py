@@ -26,14 +26,19 @@ def test_committed_tuning_table_loads():
     with open(_lib.TUNING_PATH) as f:
         table = json.load(f)
     entries = table["entries"]
-    assert [e["max_log2_n"] for e in entries] == sorted(e["max_log2_n"] for e in entries)
+    pentries = table.get("pairs_entries", [])
+    for es in (entries, pentries):
+        assert [e["max_log2_n"] for e in es] == sorted(e["max_log2_n"] for e in es)
     lib = _lib.lib()
-    assert _lib.load_tuning(lib) == len(entries)
+    assert _lib.load_tuning(lib) == len(entries) + len(pentries)
     t = _lib.MmsTuning()
     for e in entries:
         assert lib.mms_get_tuning(1 << e["max_log2_n"], 0, t) == 0
         assert (t.fanout, t.merge_tile, t.variant, t.base) == (e["fanout"], e["merge_tile"], e["variant"],
                                                                e.get("base", 0))
+    for e in pentries:
+        assert lib.mms_get_tuning(1 << e["max_log2_n"], _lib.MMS_PAIRS, t) == 0
+        assert (t.fanout, t.base, t.flags) == (e["fanout"], e["base"], _lib.MMS_PAIRS)
     # pairs keep the key-value merge tile whatever the table says
     assert lib.mms_get_tuning(1 << 27, _lib.MMS_PAIRS, t) == 0 and t.merge_tile == 4096
 
@@ -45,6 +50,7 @@ def test_autotune_candidates():
     assert len(big) == len(autotune.FANOUTS) * len(autotune.TILES) * len(autotune.VARIANTS)
     assert {v for _, _, v in big} == {0, 1, 2, 3}
     assert autotune.BASES == [0, 1, 2, 3, 4, 5, 6]
+    assert autotune.PAIR_BASES == [0, 3]
 
 
 def test_traffic_is_null_when_sources_change(monkeypatch, tmp_path):
