@@ -118,3 +118,28 @@ def test_pairs_uniform_sampled(mms):
     for i in sample_positions(N_PAIRS, 3, count=3):
         key, idx = oracle.select(x, i)
         assert (int(kh[i]), int(vh[i])) == (key, idx), i
+
+
+def test_batched_fullsize(mms):
+    """The batched workload the benchmark times: 4096 uint32 arrays with sizes
+    log-uniform in [2^8, 2^20] (about 5.3e8 keys), one call.  Every segment
+    must equal its own sorted input: checked for all segments at once by
+    sorting (segment, key) composites with torch, and for a sample of
+    segments against the oracle."""
+    sizes = mmsgen.loguniform_sizes(mmsgen.seed_for(4, 0), 4096, 8, 20).astype(np.int64)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    total = int(off[-1])
+    x = mmsgen.uniform_u32(mmsgen.seed_for(4, 2), total)
+    xd = dev(x)
+    out = mms.segmented_sort(xd, off, i32=False)
+    seg = torch.repeat_interleave(torch.arange(sizes.size, device="cuda", dtype=torch.int64),
+                                  torch.from_numpy(sizes).cuda())
+    want = torch.sort((seg << 32) | (xd.to(torch.int64) & 0xFFFFFFFF)).values
+    got = (seg << 32) | (out.to(torch.int64) & 0xFFFFFFFF)
+    assert torch.equal(got, want)
+    del want, got, seg
+    oh = out.cpu().numpy().view(np.uint32)
+    rng = np.random.default_rng(7)
+    for s in sorted({0, int(np.argmax(sizes)), *rng.integers(0, sizes.size, 6).tolist()}):
+        a, b = int(off[s]), int(off[s + 1])
+        assert np.array_equal(oh[a:b], oracle.sort(x[a:b])), s
