@@ -143,3 +143,37 @@ def test_batched_fullsize(mms):
     for s in sorted({0, int(np.argmax(sizes)), *rng.integers(0, sizes.size, 6).tolist()}):
         a, b = int(off[s]), int(off[s + 1])
         assert np.array_equal(oh[a:b], oracle.sort(x[a:b])), s
+
+
+def test_keys_near_2_32(mms):
+    """The largest sizes the 32-bit positions allow: 2^32 - 778 keys (five
+    rounds), checked by sortedness and the histogram of the top 16 bits."""
+    n = (1 << 32) - 778
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    x = torch.randint(-2**31, 2**31 - 1, (n,), dtype=torch.int32, device="cuda", generator=g)
+    out = mms.sort(x, i32=False)
+    a = out.to(torch.int64) & 0xFFFFFFFF
+    assert bool((a[1:] >= a[:-1]).all())
+    del a
+    hx = torch.bincount((x.to(torch.int64) & 0xFFFFFFFF) >> 16, minlength=65536)
+    ho = torch.bincount((out.to(torch.int64) & 0xFFFFFFFF) >> 16, minlength=65536)
+    assert torch.equal(hx, ho)
+
+
+def test_pairs_above_2_31(mms):
+    """2^31 + 4097 stable pairs with 1024 distinct keys: sorted keys, values a
+    permutation that increases inside every run of equal keys."""
+    n = (1 << 31) + 4097
+    g = torch.Generator(device="cuda")
+    g.manual_seed(6)
+    x = torch.randint(0, 1024, (n,), dtype=torch.int32, device="cuda", generator=g)
+    v = torch.arange(n, dtype=torch.int64, device="cuda").to(torch.int32)
+    k, val = mms.sort_pairs(x, v, i32=False)
+    vv = val.to(torch.int64) & 0xFFFFFFFF
+    # (key, value) strictly increasing: keys sorted, equal keys in input order
+    c = (k.to(torch.int64) << 32) | vv
+    assert bool((c[1:] > c[:-1]).all())
+    del c
+    assert torch.equal(torch.bincount(x, minlength=1024), torch.bincount(k, minlength=1024))
+    assert torch.equal(x[vv], k)
