@@ -481,16 +481,17 @@ __device__ __forceinline__ void merge_pair_range_keys(const uint32_t* X, uint32_
                                                       uint32_t lb, uint32_t d0, uint32_t d1, const Sink& out,
                                                       uint32_t out_base, uint32_t* scr, int lane) {
     constexpr uint32_t N = (uint32_t)kWave * EM;
-    if (lb == 0) {
-        // a run without a partner (an odd run count at this level) is
-        // already in order: move it in the block layout the sinks take,
-        // 16-byte reads (aA, d0 and N are multiples of 4; reads past the
-        // run stay in the caller's LDS and are not stored)
+    if (la == 0 || lb == 0) {
+        // one run is empty (an odd run count at this level, or an empty
+        // piece): the other is already in order; move it in the block layout
+        // the sinks take, 16-byte reads (aA, aB, d0 and N are multiples of
+        // 4; reads past the run stay in the caller's LDS and are not stored)
+        const uint32_t a0 = lb == 0 ? aA : aB;
         for (uint32_t o = d0; o < d1; o += N) {
             uint32_t m[EM];
 #pragma unroll
             for (int c = 0; c < EM / 4; ++c) {
-                const uint4 v = *reinterpret_cast<const uint4*>(X + aA + o + (uint32_t)c * 256u + 4u * (uint32_t)lane);
+                const uint4 v = *reinterpret_cast<const uint4*>(X + a0 + o + (uint32_t)c * 256u + 4u * (uint32_t)lane);
                 m[4 * c] = v.x;
                 m[4 * c + 1] = v.y;
                 m[4 * c + 2] = v.z;
