@@ -267,6 +267,12 @@ __device__ __forceinline__ void merge_pair_range(const uint32_t* Xk, const uint3
                                                  uint32_t aB, uint32_t lb, uint32_t d0, uint32_t d1,
                                                  const Sink& out, uint32_t out_base, int lane) {
     constexpr uint32_t N = (uint32_t)kWave * EM;
+    if (la == 0 || lb == 0) {   // one run is empty: the other is already in order
+        const uint32_t a0 = lb == 0 ? aA : aB;
+        for (uint32_t k = d0 + (uint32_t)lane; k < d1; k += (uint32_t)kWave)
+            out.put(out_base + k, lds_get<P>(Xk, Xv, a0 + k));
+        return;
+    }
     uint32_t p = lds_corank2(Xk, aA, la, aB, lb, d0, lane);
     uint32_t q = d0 - p;
     for (uint32_t o = d0; o < d1; o += N) {
