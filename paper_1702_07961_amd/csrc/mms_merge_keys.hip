@@ -10,9 +10,11 @@
 // Memory latency is hidden by a three-stage pipeline: as tile t starts, the
 // keys of tile t+G are loaded into registers in 16-byte chunks (each thread
 // holds a few chunks with their LDS destinations) and land in the LDS buffer
-// that tile t's last level does not read; wave 0 meanwhile builds the piece
-// table and per-level wave plan of tile t+2G from split indices it fetched
-// one tile earlier with scalar loads.
+// that tile t's last level does not read.  The piece table of a tile is
+// built in two steps one tile apart, by three waves besides their share of
+// the merge: wave 0 lays out the pieces of tile t+3G from split indices it
+// fetched one tile earlier with scalar loads, then waves 1 and 2 derive the
+// chunk table and the per-level wave plan of tile t+2G from its layout.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -119,7 +121,8 @@ __device__ __forceinline__ uint32_t excl_scan16(uint32_t x, int lane) {
 // multiples of 4; a pair holding no midpoint goes whole to the wave whose
 // share holds its start.  No quantity reaches 2^22 (udiv_small's range).
 template <int W>
-__device__ __forceinline__ void build_plan(const Meta& m, uint32_t Kg, uint32_t total, int lane) {
+__device__ __forceinline__ void build_plan(const Meta& m, uint32_t Kg, int lane) {
+    const uint32_t total = m.plen[Kg];
     const uint32_t l = (uint32_t)lane >> 4, w = (uint32_t)lane & 15u;
     uint32_t nlev = 0;
     while ((1u << nlev) < Kg) ++nlev;
@@ -155,8 +158,8 @@ __device__ __forceinline__ void build_plan(const Meta& m, uint32_t Kg, uint32_t 
     }
 }
 
-template <int W>
-__device__ __forceinline__ void build_meta(const Meta& m, uint32_t s, uint32_t e, const TileGeo& g, int lane) {
+// Piece layout: start, plen and sbeg of every run and their totals.
+__device__ __forceinline__ void build_pieces(const Meta& m, uint32_t s, uint32_t e, const TileGeo& g, int lane) {
     const bool own = (uint32_t)lane < g.Kg;
     uint32_t len = own ? e - s : 0u;
     uint32_t pl = excl_scan16(len, lane);
@@ -175,10 +178,13 @@ __device__ __forceinline__ void build_meta(const Meta& m, uint32_t s, uint32_t e
         m.plen[g.Kg] = tot_pl;
         m.sbeg[g.Kg] = tot_sb;
     }
-    lds_wave_sync();
-    // chunk table: largest k < Kg with sbeg[k] <= 64*c
+}
+
+// Chunk table from the piece layout: largest k < Kg with sbeg[k] <= 64*c.
+__device__ __forceinline__ void build_chunks(const Meta& m, uint32_t Kg, int lane) {
+    const uint32_t tot_sb = m.sbeg[Kg];
     for (uint32_t c = (uint32_t)lane; c * 64u < tot_sb; c += 64u) {
-        uint32_t lo = 0, hi = g.Kg;
+        uint32_t lo = 0, hi = Kg;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
             if (m.sbeg[mid] <= c * 64u) lo = mid;
@@ -186,7 +192,15 @@ __device__ __forceinline__ void build_meta(const Meta& m, uint32_t s, uint32_t e
         }
         m.cseg[c] = lo;
     }
-    build_plan<W>(m, g.Kg, tot_pl, lane);
+}
+
+// The whole piece table by one wave (the pipeline's prologue).
+template <int W>
+__device__ __forceinline__ void build_meta(const Meta& m, uint32_t s, uint32_t e, const TileGeo& g, int lane) {
+    build_pieces(m, s, e, g, lane);
+    lds_wave_sync();
+    build_chunks(m, g.Kg, lane);
+    build_plan<W>(m, g.Kg, lane);
 }
 
 }  // namespace
@@ -207,7 +221,8 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
     uint32_t* scr = smem + 2 * cap;
     // the block merge reads up to 64*EM words past a buffer's last run
     static_assert(W * Xpose<EM>::WORDS >= 64u * EM, "LDS after bufB is shorter than a merge block");
-    uint32_t* mbase = scr + W * Xpose<EM>::WORDS;     // three piece tables of kMetaWords
+    static_assert(W >= 3, "waves 0, 1 and 2 build the piece tables");
+    uint32_t* mbase = scr + W * Xpose<EM>::WORDS;     // four piece tables of kMetaWords
     auto meta = [&](int which) {
         uint32_t* mb = mbase + kMetaWords * (uint32_t)which;
         return Meta{mb, mb + 17, mb + 34, mb + 51, mb + 51 + kPlanWords};
@@ -226,7 +241,7 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
     // registers of the prefetch stage: chunks of 4 LDS slots per thread
     uint4 pf_val[PC];
     uint32_t pf_dst[PC];
-    uint32_t nx_s = 0, nx_e = 0;   // wave 0: split indices of tile t+2G (at loop start)
+    uint32_t nx_s = 0, nx_e = 0;   // wave 0: split indices of tile t+3G (at loop start)
 
     // Chunk P (a multiple of 4 in LDS slot coordinates) lies in piece k with
     // sbeg[k] <= P < sbeg[k] + len_k rounded up to 4, so off = P - sbeg[k] <
@@ -264,12 +279,14 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
             if (pf_dst[r] != 0xFFFFFFFFu) *reinterpret_cast<uint4*>(X + pf_dst[r]) = pf_val[r];
     };
 
-    // prologue: piece table and keys of the first tile, split of the second
     // Pipeline: while tile t is merged, the keys of tile t+G are in flight
-    // (issued as tile t starts) and wave 0 prepares the piece table of tile
-    // t+2G from split indices it loaded one tile earlier.  Three piece tables
-    // rotate (tiles t, t+G, t+2G).
-    auto nxt = [](int i) { return i == 2 ? 0 : i + 1; };
+    // (issued as tile t starts), waves 1 and 2 finish the piece table of tile
+    // t+2G and wave 0 lays out the pieces of tile t+3G from split indices it
+    // loaded one tile earlier.  Four piece tables rotate (tiles t .. t+3G);
+    // every step reads what an earlier tile's barriers published.
+    // Prologue: whole piece tables of the first two tiles, the layout of the
+    // third, the split indices of the fourth, and the first tile's keys.
+    auto nxt = [](int i) { return (i + 1) & 3; };
     TileGeo g = tile_geo(ph, b, t, ra, lL);
     TileGeo g1 = tile_geo(ph, b, t + G < tiles ? t + G : t, ra, lL);
     {
@@ -280,8 +297,13 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
             if (t + G < tiles) {
                 load_split(table, t + G, g1, L, K, lane, s, e);
                 build_meta<W>(meta(1), s, e, g1, lane);
-                if (t + 2 * G < tiles)
-                    load_split(table, t + 2 * G, tile_geo(ph, b, t + 2 * G, ra, lL), L, K, lane, nx_s, nx_e);
+                if (t + 2 * G < tiles) {
+                    const TileGeo gp = tile_geo(ph, b, t + 2 * G, ra, lL);
+                    load_split(table, t + 2 * G, gp, L, K, lane, s, e);
+                    build_pieces(meta(2), s, e, gp, lane);
+                    if (t + 3 * G < tiles)
+                        load_split(table, t + 3 * G, tile_geo(ph, b, t + 3 * G, ra, lL), L, K, lane, nx_s, nx_e);
+                }
             }
         }
         lds_barrier();
@@ -310,11 +332,18 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
         // geometry of tile t+2G (of tile t when there is none: no select
         // between structs is needed)
         const TileGeo g2 = tile_geo(ph, b, has2 ? t2 : t, ra, lL);
-        // wave 0: piece table of tile t+2G, split indices of tile t+3G
-        if (wave == 0 && has2) {
-            build_meta<W>(meta(nxt(nxt(cur))), nx_s, nx_e, g2, lane);
-            if (t2 + G < tiles)
-                load_split(table, t2 + G, tile_geo(ph, b, t2 + G, ra, lL), L, K, lane, nx_s, nx_e);
+        // waves 1 and 2: chunk table and wave plan of tile t+2G; wave 0:
+        // piece layout of tile t+3G, split indices of tile t+4G
+        if (has2) {
+            const Meta m2 = meta(nxt(nxt(cur)));
+            if (wave == 1) build_chunks(m2, g2.Kg, lane);
+            if (wave == 2) build_plan<W>(m2, g2.Kg, lane);
+            const uint64_t t3 = t2 + G;
+            if (wave == 0 && t3 < tiles) {
+                build_pieces(meta(nxt(nxt(nxt(cur)))), nx_s, nx_e, tile_geo(ph, b, t3, ra, lL), lane);
+                if (t3 + G < tiles)
+                    load_split(table, t3 + G, tile_geo(ph, b, t3 + G, ra, lL), L, K, lane, nx_s, nx_e);
+            }
         }
 
         uint32_t* X = in;
@@ -375,7 +404,7 @@ static hipError_t launch_variant(const Phase& ph, const Bufs& b, const RoundArgs
     // chunks of 4 slots per thread: a tile holds at most kToutKeys keys plus
     // up to 3 padding slots per piece
     constexpr int PC = (int)((kToutKeys + 4u * kMaxFanout + 4u * W * 64u - 1u) / (4u * W * 64u));
-    const size_t lds = (2u * (ra.Tout + 4u * ra.K) + W * Xpose<EM>::WORDS + 3u * kMetaWords) * sizeof(uint32_t);
+    const size_t lds = (2u * (ra.Tout + 4u * ra.K) + W * Xpose<EM>::WORDS + 4u * kMetaWords) * sizeof(uint32_t);
     hipError_t e = allow_lds((const void*)k_merge_keys<EM, W, PC, MINW>, lds);
     if (e != hipSuccess) return e;
     // persistent grid: as many workgroups as fit in the LDS of `grid` CUs
