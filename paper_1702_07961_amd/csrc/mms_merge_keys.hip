@@ -104,13 +104,14 @@ struct Meta {
 constexpr uint32_t kPlanWords = 4u * 16u * 2u;
 constexpr uint32_t kMetaWords = 3u * 17u + kPlanWords + (kToutKeys + 4u * kMaxFanout) / 64u + 1u;
 
-__device__ __forceinline__ uint32_t excl_scan16(uint32_t x, int lane) {
+// Exclusive sum over the 16 lanes of each row (DPP row shifts; a lane
+// shifted in from outside the row reads 0).
+__device__ __forceinline__ uint32_t excl_scan16(uint32_t x) {
     uint32_t incl = x;
-#pragma unroll
-    for (int d = 1; d < 16; d <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)incl, d, 64);
-        if ((lane & 15) >= d) incl += y;
-    }
+    incl += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)incl, 0x111, 0xF, 0xF, false);   // row_shr:1
+    incl += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)incl, 0x112, 0xF, 0xF, false);   // row_shr:2
+    incl += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)incl, 0x114, 0xF, 0xF, false);   // row_shr:4
+    incl += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)incl, 0x118, 0xF, 0xF, false);   // row_shr:8
     return incl - x;
 }
 
@@ -130,11 +131,17 @@ __device__ __forceinline__ void build_plan(const Meta& m, uint32_t Kg, int lane)
     const uint32_t nseg = act ? (Kg + (1u << l) - 1u) >> l : 0u;
     const uint32_t npairs = (nseg + 1u) >> 1;
     const uint32_t mid2 = (2u * w + 1u) * total;           // 2W * midpoint
+    // output start of pair i of the level (i <= 8), read once
+    uint32_t pst[9];
+#pragma unroll
+    for (uint32_t i = 0; i < 9u; ++i) pst[i] = m.plen[min((2u * i) << l, Kg)];
     uint32_t iw = 0;
-    for (uint32_t i = 1; i < npairs; ++i)
-        if (2u * (uint32_t)W * m.plen[min((2u * i) << l, Kg)] <= mid2) iw = i;
+#pragma unroll
+    for (uint32_t i = 1; i < 8u; ++i)
+        if (i < npairs && 2u * (uint32_t)W * pst[i] <= mid2) iw = i;
     const uint64_t grp = 0xFFFFull << (16u * (l & 3u));
     uint32_t v0 = 0, nw = 1, own = 0;
+#pragma unroll
     for (uint32_t i = 0; i < 8u; ++i) {
         const uint64_t mi = __ballot(act && i < npairs && iw == i) & grp;
         if (act && i == iw && mi) {
@@ -142,14 +149,18 @@ __device__ __forceinline__ void build_plan(const Meta& m, uint32_t Kg, int lane)
             nw = (uint32_t)__popcll(mi);
         }
         if (act && i < npairs && mi == 0ull && total) {
-            const uint32_t p0 = m.plen[min((2u * i) << l, Kg)];
-            const uint32_t o = min(udiv_small(p0 * (uint32_t)W, total), (uint32_t)W - 1u);
+            const uint32_t o = min(udiv_small(pst[i] * (uint32_t)W, total), (uint32_t)W - 1u);
             if (o == w) own |= 1u << i;
         }
     }
     if (act) {
-        const uint32_t p0 = m.plen[min((2u * iw) << l, Kg)];
-        const uint32_t p2 = m.plen[min((2u * iw + 2u) << l, Kg)];
+        uint32_t p0 = pst[0], p2 = pst[1];
+#pragma unroll
+        for (uint32_t i = 1; i < 8u; ++i)
+            if (iw == i) {
+                p0 = pst[i];
+                p2 = pst[i + 1u];
+            }
         const uint32_t sz = p2 - p0, j = w - v0;
         const uint32_t d0 = total ? udiv_small(sz * j, nw) & ~3u : 0u;
         const uint32_t d1 = !total ? 0u : (j + 1u == nw ? sz : udiv_small(sz * (j + 1u), nw) & ~3u);
@@ -162,18 +173,18 @@ __device__ __forceinline__ void build_plan(const Meta& m, uint32_t Kg, int lane)
 __device__ __forceinline__ void build_pieces(const Meta& m, uint32_t s, uint32_t e, const TileGeo& g, int lane) {
     const bool own = (uint32_t)lane < g.Kg;
     uint32_t len = own ? e - s : 0u;
-    uint32_t pl = excl_scan16(len, lane);
+    uint32_t pl = excl_scan16(len);
     // guards for memory safety only: keep the pieces inside the tile
     len = pl >= g.cnt ? 0u : min(len, g.cnt - pl);
     pl = min(pl, g.cnt);
-    const uint32_t sb = excl_scan16((len + 3u) & ~3u, lane);
+    const uint32_t sb = excl_scan16((len + 3u) & ~3u);
     if (own) {
         m.start[lane] = s;
         m.plen[lane] = pl;
         m.sbeg[lane] = sb;
     }
-    const uint32_t tot_pl = (uint32_t)__shfl((int)(pl + len), (int)(g.Kg - 1), 64);
-    const uint32_t tot_sb = (uint32_t)__shfl((int)(sb + ((len + 3u) & ~3u)), (int)(g.Kg - 1), 64);
+    const uint32_t tot_pl = (uint32_t)__builtin_amdgcn_readlane((int)(pl + len), (int)(g.Kg - 1u));
+    const uint32_t tot_sb = (uint32_t)__builtin_amdgcn_readlane((int)(sb + ((len + 3u) & ~3u)), (int)(g.Kg - 1u));
     if (lane == 0) {
         m.plen[g.Kg] = tot_pl;
         m.sbeg[g.Kg] = tot_sb;
