@@ -9,6 +9,10 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The GPU library never loads it, and it
 shares no code with the GPU path.  The C source is ``oracle.c``; ``build()``
 compiles it with gcc into ``liboracle.so`` next to this file.
+
+``cpu_parallel.cpp`` (``parallel_sort*`` below) is not part of the oracle: it
+is a multi-core CPU sort (libstdc++ parallel mode) that the benchmark's
+CPU-baseline leg times as context beside the oracle; no check relies on it.
 """
 from __future__ import annotations
 
@@ -28,13 +32,66 @@ _u32p = ctypes.POINTER(ctypes.c_uint32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 
 
+_PAR_SRC = os.path.join(_HERE, "cpu_parallel.cpp")
+_PAR_LIB = os.path.join(_HERE, "libcpuparallel.so")
+
+
 def build(src: str = _SRC, out: str = _LIB) -> str:
-    """Compile the oracle with gcc (no vector intrinsics, plain C)."""
+    """Compile the oracle with gcc (no vector intrinsics, plain C); when
+    building the default library, also the multi-core context sort."""
     tmp = out + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared",
                            "-fPIC", src, "-o", tmp])
     os.replace(tmp, out)
+    if src == _SRC:
+        build_parallel()
     return out
+
+
+def build_parallel() -> str:
+    tmp = _PAR_LIB + ".tmp"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-Wall", "-shared", "-fPIC",
+                           _PAR_SRC, "-o", tmp])
+    os.replace(tmp, _PAR_LIB)
+    return _PAR_LIB
+
+
+_par = None
+
+
+def _get_parallel():
+    global _par
+    if _par is None:
+        if not os.path.exists(_PAR_LIB):
+            build_parallel()
+        lib = ctypes.CDLL(_PAR_LIB)
+        lib.cpu_parallel_threads.restype = ctypes.c_int
+        lib.cpu_parallel_sort_u32.argtypes = [_u32p, ctypes.c_uint64, ctypes.c_uint32]
+        lib.cpu_parallel_sort_pairs_u32.argtypes = [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32]
+        lib.cpu_parallel_sort_u64.argtypes = [_u64p, ctypes.c_uint64]
+        _par = lib
+    return _par
+
+
+def parallel_threads() -> int:
+    """OpenMP threads the multi-core context sort runs on."""
+    return int(_get_parallel().cpu_parallel_threads())
+
+
+def parallel_sort(keys, vals=None, i32: bool = False):
+    """Multi-core context sort (not the oracle): sorts copies, returns them."""
+    lib = _get_parallel()
+    if keys.dtype == np.uint64:
+        k = np.array(keys, dtype=np.uint64, copy=True)
+        lib.cpu_parallel_sort_u64(_p64(k), k.size)
+        return k
+    k = np.array(keys, dtype=np.uint32, copy=True)
+    if vals is None:
+        lib.cpu_parallel_sort_u32(_p32(k), k.size, KEY_I32 if i32 else 0)
+        return k
+    v = np.array(vals, dtype=np.uint32, copy=True)
+    lib.cpu_parallel_sort_pairs_u32(_p32(k), _p32(v), k.size, KEY_I32 if i32 else 0)
+    return k, v
 
 
 _lib = None
@@ -53,6 +110,8 @@ def load(path: str = _LIB) -> ctypes.CDLL:
     lib.oracle_select.argtypes = [_u32p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                   _u32p, _u64p]
     lib.oracle_select.restype = ctypes.c_int
+    lib.oracle_sort_u64.argtypes = [_u64p, _u64p, _u64p, _u64p, ctypes.c_uint64, ctypes.c_uint32]
+    lib.oracle_sort_u64.restype = ctypes.c_int
     return lib
 
 
@@ -90,6 +149,26 @@ def sort(keys, vals=None, i32: bool = False, lib=None):
     rc = lib.oracle_sort(_p32(k), _p32(v), _p32(ok), _p32(ov), k.size, KEY_I32 if i32 else 0)
     if rc:
         raise RuntimeError(f"oracle_sort failed: {rc}")
+    return ok if vals is None else (ok, ov)
+
+
+KEY_I64 = 2
+
+
+def sort_u64(keys, vals=None, i64: bool = False, lib=None):
+    """Stable ascending sort of 64-bit keys (and 64-bit values when given)."""
+    lib = lib or _get()
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    ok = np.empty_like(k)
+    v = ov = None
+    if vals is not None:
+        v = np.ascontiguousarray(vals, dtype=np.uint64)
+        assert v.shape == k.shape
+        ov = np.empty_like(v)
+    rc = lib.oracle_sort_u64(_p64(k), None if v is None else _p64(v), _p64(ok),
+                             None if ov is None else _p64(ov), k.size, KEY_I64 if i64 else 0)
+    if rc:
+        raise RuntimeError(f"oracle_sort_u64 failed: {rc}")
     return ok if vals is None else (ok, ov)
 
 

@@ -25,6 +25,9 @@
  * are contiguous ranges of the current array in input order, so this order
  * equals (key, input index) and the merge is stable.
  *
+ * oracle_sort_u64 is the same sort for 64-bit keys and values (§6.3 also
+ * sorts 8-byte integers).
+ *
  * Also provided, each a direct transcription of a definition:
  *   oracle_partition  the split indices of §4.1 (parallel partitioning) by
  *                     merging K runs and counting, the brute-force way
@@ -281,4 +284,137 @@ int oracle_select(const uint32_t* keys, uint64_t n, uint64_t i, uint32_t flags,
         }
     }
     return ORACLE_EINVAL;   /* unreachable for consistent input */
+}
+
+/* ======================================================================== */
+/* 64-bit keys.  §6.3 also sorts 8-byte integers; the definition is the same
+ * with 64-bit keys and values: the output is the unique permutation p making
+ * (x_{p(i)}, p(i)) strictly increasing, keys compared as unsigned 64-bit
+ * integers, or as signed ones with ORACLE_KEY_I64.  Same method as the 32-bit
+ * sort above (runs of 1, fan-out 5, a min-heap over (key, run) per group),
+ * written out again for 64-bit keys rather than shared, so a slip in one
+ * width cannot hide behind the other.                                      */
+/* ======================================================================== */
+
+#define ORACLE_KEY_I64 2u
+
+static int key64_less(uint64_t a, uint64_t b, int i64) {
+    if (i64) return (int64_t)a < (int64_t)b;
+    return a < b;
+}
+
+typedef struct {
+    uint64_t key;
+    uint32_t run;
+} hnode64_t;
+
+static int hnode64_less(hnode64_t a, hnode64_t b, int i64) {
+    if (key64_less(a.key, b.key, i64)) return 1;
+    if (key64_less(b.key, a.key, i64)) return 0;
+    return a.run < b.run;
+}
+
+typedef struct {
+    hnode64_t* v;
+    int size;
+    int i64;
+} heap64_t;
+
+static void heap64_push(heap64_t* h, hnode64_t x) {
+    int i = h->size++;
+    h->v[i] = x;
+    while (i > 0) {
+        int parent = (i - 1) / 2;
+        if (!hnode64_less(h->v[i], h->v[parent], h->i64)) break;
+        hnode64_t t = h->v[i]; h->v[i] = h->v[parent]; h->v[parent] = t;
+        i = parent;
+    }
+}
+
+static hnode64_t heap64_pop(heap64_t* h) {
+    hnode64_t top = h->v[0];
+    h->v[0] = h->v[--h->size];
+    int i = 0;
+    for (;;) {
+        int l = 2 * i + 1, r = 2 * i + 2, m = i;
+        if (l < h->size && hnode64_less(h->v[l], h->v[m], h->i64)) m = l;
+        if (r < h->size && hnode64_less(h->v[r], h->v[m], h->i64)) m = r;
+        if (m == i) break;
+        hnode64_t t = h->v[i]; h->v[i] = h->v[m]; h->v[m] = t;
+        i = m;
+    }
+    return top;
+}
+
+static void merge_runs64(const uint64_t* src_k, const uint64_t* src_v,
+                         uint64_t* dst_k, uint64_t* dst_v,
+                         const uint64_t* starts, int nruns, int i64) {
+    hnode64_t hv[ORACLE_FANOUT];
+    uint64_t next[ORACLE_FANOUT];
+    heap64_t h = { hv, 0, i64 };
+    for (int j = 0; j < nruns; ++j) {
+        next[j] = starts[j];
+        if (next[j] < starts[j + 1]) {
+            hnode64_t x = { src_k[next[j]], (uint32_t)j };
+            heap64_push(&h, x);
+        }
+    }
+    uint64_t out = starts[0];
+    while (h.size > 0) {
+        hnode64_t x = heap64_pop(&h);
+        int j = (int)x.run;
+        dst_k[out] = src_k[next[j]];
+        if (dst_v) dst_v[out] = src_v[next[j]];
+        ++out;
+        ++next[j];
+        if (next[j] < starts[j + 1]) {
+            hnode64_t y = { src_k[next[j]], (uint32_t)j };
+            heap64_push(&h, y);
+        }
+    }
+}
+
+/*
+ * Stable ascending sort of n 64-bit keys (and 64-bit values, if vals !=
+ * NULL); same conventions as oracle_sort.
+ */
+int oracle_sort_u64(const uint64_t* keys, const uint64_t* vals,
+                    uint64_t* out_keys, uint64_t* out_vals,
+                    uint64_t n, uint32_t flags) {
+    if ((vals == NULL) != (out_vals == NULL)) return ORACLE_EINVAL;
+    if (n == 0) return ORACLE_OK;
+    if (!keys || !out_keys) return ORACLE_EINVAL;
+    int i64 = (flags & ORACLE_KEY_I64) != 0;
+
+    uint64_t* a_k = (uint64_t*)malloc(n * sizeof(uint64_t));
+    uint64_t* b_k = (uint64_t*)malloc(n * sizeof(uint64_t));
+    uint64_t* a_v = vals ? (uint64_t*)malloc(n * sizeof(uint64_t)) : NULL;
+    uint64_t* b_v = vals ? (uint64_t*)malloc(n * sizeof(uint64_t)) : NULL;
+    if (!a_k || !b_k || (vals && (!a_v || !b_v))) {
+        free(a_k); free(b_k); free(a_v); free(b_v);
+        return ORACLE_ENOMEM;
+    }
+    memcpy(a_k, keys, n * sizeof(uint64_t));
+    if (vals) memcpy(a_v, vals, n * sizeof(uint64_t));
+
+    for (uint64_t len = 1; len < n; len *= ORACLE_FANOUT) {
+        for (uint64_t g = 0; g < n; g += len * ORACLE_FANOUT) {
+            uint64_t starts[ORACLE_FANOUT + 1];
+            int nruns = 0;
+            for (int j = 0; j <= ORACLE_FANOUT; ++j) {
+                uint64_t s = g + (uint64_t)j * len;
+                starts[j] = s < n ? s : n;
+            }
+            for (int j = 0; j < ORACLE_FANOUT; ++j)
+                if (starts[j] < starts[j + 1]) nruns = j + 1;
+            merge_runs64(a_k, a_v, b_k, b_v, starts, nruns, i64);
+        }
+        uint64_t* t = a_k; a_k = b_k; b_k = t;
+        t = a_v; a_v = b_v; b_v = t;
+    }
+
+    memcpy(out_keys, a_k, n * sizeof(uint64_t));
+    if (vals) memcpy(out_vals, a_v, n * sizeof(uint64_t));
+    free(a_k); free(b_k); free(a_v); free(b_v);
+    return ORACLE_OK;
 }

@@ -49,3 +49,25 @@ def partition_cases():
     keys = np.array([k for run in runs for k in run], dtype=np.uint32)
     offs = np.cumsum([0] + [len(r) for r in runs]).astype(np.uint64)
     return keys, offs, splits
+
+
+def sort_cases_u64():
+    """Yield (name, i64, in_keys, out_keys, idx) from hand_cases_u64.txt."""
+    cases = []
+    cur = None
+    with open(os.path.join(GOLDEN, "hand_cases_u64.txt")) as f:
+        for line in f:
+            line = line.rstrip("\n")
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("case "):
+                _, name, kind = line.split()
+                cur = {"name": name, "i64": kind == "i64"}
+                cases.append(cur)
+            elif line.startswith("in:"):
+                cur["in"] = np.array([int(t, 16) for t in line[3:].split()], dtype=np.uint64)
+            elif line.startswith("out:"):
+                cur["out"] = np.array([int(t, 16) for t in line[4:].split()], dtype=np.uint64)
+            elif line.startswith("idx:"):
+                cur["idx"] = np.array([int(t) for t in line[4:].split()], dtype=np.uint64)
+    return [(c["name"], c["i64"], c["in"], c["out"], c["idx"]) for c in cases]
