@@ -11,7 +11,9 @@ import json
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libmms.so")
+# MMS_LIBRARY names another build of the same library (the sanitizer builds
+# of paper_1702_07961_amd.build); by default the in-tree libmms.so
+LIB_PATH = os.environ.get("MMS_LIBRARY") or os.path.join(PKG, "libmms.so")
 # tuning table written by paper_1702_07961_amd.autotune; MMS_TUNING_FILE
 # overrides the path, an empty value keeps the library's built-in default
 TUNING_PATH = os.path.join(PKG, "tuning_mi355x.json")
@@ -26,11 +28,14 @@ MMS_ESHUTDOWN = -5
 
 MMS_PAIRS = 0x1
 MMS_KEY_I32 = 0x2
+MMS_KEY_I64 = 0x4
+MMS_KEYS64 = 0x8
+MMS_MERGEPATH = 0x10
 
 # every symbol include/mms.h declares
 EXPORTS = [
     "mms_last_error", "mms_version", "mms_plan", "mms_workspace_bytes", "mms_sort_u32",
-    "mms_sort_pairs_u32", "mms_partition_u32", "mms_copy_u32", "mms_timing_enable",
+    "mms_sort_pairs_u32", "mms_sort_u64", "mms_sort_pairs_u64", "mms_sort_mergepath_u32", "mms_partition_u32", "mms_copy_u32", "mms_timing_enable",
     "mms_timing_reset", "mms_timing_read", "mms_segmented_workspace_bytes", "mms_segmented_sort",
     "mms_set_tuning", "mms_get_tuning", "mms_server_create", "mms_submit", "mms_poll", "mms_wait",
     "mms_release", "mms_server_get_stats", "mms_server_destroy",
@@ -148,6 +153,12 @@ def _declare(lib):
     lib.mms_sort_u32.restype = ctypes.c_int
     lib.mms_sort_pairs_u32.argtypes = [_vp, _vp, _vp, _vp, _u64, _vp, ctypes.c_size_t, _u32, _vp]
     lib.mms_sort_pairs_u32.restype = ctypes.c_int
+    lib.mms_sort_mergepath_u32.argtypes = [_vp, _vp, _u64, _vp, ctypes.c_size_t, _u32, _vp]
+    lib.mms_sort_mergepath_u32.restype = ctypes.c_int
+    lib.mms_sort_u64.argtypes = [_vp, _vp, _u64, _vp, ctypes.c_size_t, _u32, _vp]
+    lib.mms_sort_u64.restype = ctypes.c_int
+    lib.mms_sort_pairs_u64.argtypes = [_vp, _vp, _vp, _vp, _u64, _vp, ctypes.c_size_t, _u32, _vp]
+    lib.mms_sort_pairs_u64.restype = ctypes.c_int
     lib.mms_partition_u32.argtypes = [_vp, _u64, _u64, _u32, _vp, _vp, _u64, _vp, _u32, _vp]
     lib.mms_partition_u32.restype = ctypes.c_int
     lib.mms_copy_u32.argtypes = [_vp, _vp, _u64, _vp]
