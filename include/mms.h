@@ -46,6 +46,9 @@ extern "C" {
 /* flags */
 #define MMS_PAIRS 0x1u    /* workspace sizing: key-value pairs                */
 #define MMS_KEY_I32 0x2u  /* keys are int32 (signed order) instead of uint32  */
+#define MMS_KEY_I64 0x4u  /* 64-bit keys are int64 (signed order)             */
+#define MMS_KEYS64 0x8u   /* plan / workspace sizing: 64-bit keys (and values) */
+#define MMS_MERGEPATH 0x10u /* plan / workspace sizing: the merge-path baseline */
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* mms_last_error(void);
@@ -98,6 +101,44 @@ int mms_sort_pairs_u32(const uint32_t* d_kin, const uint32_t* d_vin,
                        void* d_ws, size_t ws_bytes, uint32_t flags, void* stream);
 
 /*
+ * 64-bit keys (§6.3 also sorts 8-byte integers): the same method on 64-bit
+ * keys, and stable pairs of 64-bit keys and 64-bit values.
+ *
+ * mms_sort_u64 sorts n keys ascending: uint64 order, or int64 order with
+ * MMS_KEY_I64.  mms_sort_pairs_u64 sorts n (key, value) pairs stably by key
+ * (equal keys keep their input order, so the result is unique).  d_in /
+ * d_out (d_kin / d_kout, d_vin / d_vout) hold n 8-byte elements and may be
+ * the same buffer, but must not partially overlap; keys and values must not
+ * overlap each other.  d_ws holds at least
+ * mms_workspace_bytes(n, MMS_KEYS64 [| MMS_PAIRS]) bytes, 256-byte aligned,
+ * disjoint from the data; mms_plan with MMS_KEYS64 reports the tile, fan-out
+ * and passes.  Asynchronous on `stream` like every sort.  Errors:
+ * MMS_EINVAL (pointers, overlap, workspace, flags other than MMS_KEY_I64,
+ * n >= 2^32), MMS_EHIP (launch failure).
+ */
+int mms_sort_u64(const uint64_t* d_in, uint64_t* d_out, uint64_t n,
+                 void* d_ws, size_t ws_bytes, uint32_t flags, void* stream);
+int mms_sort_pairs_u64(const uint64_t* d_kin, const uint64_t* d_vin,
+                       uint64_t* d_kout, uint64_t* d_vout, uint64_t n,
+                       void* d_ws, size_t ws_bytes, uint32_t flags, void* stream);
+
+/*
+ * Baseline for comparison, not the paper's method: a pairwise merge-path
+ * mergesort of the kind the paper measures against (§1 and §6.4: two-way
+ * merges in which every thread finds its start on the merge path by binary
+ * search and merges its outputs one at a time from shared memory, at
+ * addresses that depend on the keys, so bank conflicts depend on the input).
+ * Tiles of 3840 keys (256 threads x 15) are sorted in a workgroup by
+ * per-thread sorts and eight levels of such merges; then ceil(log2(tiles))
+ * merge passes follow, each a partition launch and a merge launch.  Keys
+ * only, ascending: uint32, or int32 with MMS_KEY_I32.  Same buffer rules as
+ * mms_sort_u32; d_ws holds mms_workspace_bytes(n, MMS_MERGEPATH) bytes.
+ * Errors: MMS_EINVAL, MMS_EHIP.
+ */
+int mms_sort_mergepath_u32(const uint32_t* d_in, uint32_t* d_out, uint64_t n,
+                           void* d_ws, size_t ws_bytes, uint32_t flags, void* stream);
+
+/*
  * §4.1 parallel partitioning on its own: split indices of groups of K sorted
  * runs at given ranks.  The n elements of d_keys form groups of K runs laid
  * out back to back: run k of group g starts at g*K*run_len + k*run_len and
@@ -136,11 +177,18 @@ int mms_copy_u32(const uint32_t* d_in, uint32_t* d_out, uint64_t n, void* stream
  * every segment's tiles (the base case, then per round the partition and
  * the merge).  The first call with a given (offsets, pointers, flags,
  * tuning) captures those launches into a hipGraph, and later calls with the
- * same signature replay it with a single graph launch on `stream`.  The
- * library keeps, per captured signature (up to 8, least recently used
- * evicted), the per-tile task lists in device memory it allocates itself.
+ * same signature replay it with a single graph launch on `stream`.
+ *
+ * Memory: all device memory is the caller's.  The workspace holds the
+ * ping-pong buffers, the partition table and the batch metadata (a 64-byte
+ * descriptor per non-empty segment and 8 bytes per tile task).  The library
+ * keeps, per captured signature (up to 8, least recently used evicted), a
+ * host image of that metadata in pinned host memory, and every call copies
+ * it into the workspace with an asynchronous copy on `stream` ahead of the
+ * launches, so the workspace may be used for anything else between calls.
+ * An evicted signature is torn down only after its last launch completes.
  * Errors: MMS_EINVAL (offsets decreasing, buffers, workspace), MMS_ENOMEM
- * (task lists), MMS_EHIP (capture or launch).
+ * (pinned staging of the metadata), MMS_EHIP (capture, copy or launch).
  */
 size_t mms_segmented_workspace_bytes(const uint64_t* h_offsets, uint64_t num_segs, uint32_t flags);
 int mms_segmented_sort(const uint32_t* d_kin, uint32_t* d_kout, const uint32_t* d_vin, uint32_t* d_vout,
@@ -161,7 +209,8 @@ int mms_segmented_sort(const uint32_t* d_kin, uint32_t* d_kout, const uint32_t* 
  *   variant     keys-only merge kernel shape (0: 64x16-key blocks, 8 waves;
  *               1: 64x8-key blocks, 16 waves; 2: 64x8-key blocks, 8 waves;
  *               3: as 2 with two workgroups per compute unit, for merge tiles
- *               up to 7168)
+ *               up to 7168; 4: the minBlockHeap of §4.2, one heap of
+ *               64-key nodes per wave and one merge tile per wave)
  *   base        base-case shape, keys per lane x waves (§4.3's base case
  *               sorts one tile per workgroup): 0: 8 x 4, 1: 4 x 8, 2: 16 x 2,
  *               all 2048-key tiles; 3: 8 x 8 and 5: 16 x 4, 4096-key tiles;

@@ -59,10 +59,11 @@ def _get():
             ("mmsgen_loguniform_sizes", [ctypes.c_uint64, _u64p, ctypes.c_uint64,
                                          ctypes.c_double, ctypes.c_double]),
             ("mmsgen_unit_doubles", [ctypes.c_uint64, _f64p, ctypes.c_uint64]),
+            ("mmsgen_mergepath_adversary_u32", [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint64]),
         ]:
             f = getattr(lib, name)
             f.argtypes = args
-            f.restype = ctypes.c_int if name == "mmsgen_stride64_u32" else None
+            f.restype = ctypes.c_int if name in ("mmsgen_stride64_u32", "mmsgen_mergepath_adversary_u32") else None
         _lib = lib
     return _lib
 
@@ -135,6 +136,19 @@ def poisson_arrivals(seed: int, count: int, rate: float) -> np.ndarray:
     return np.cumsum(-np.log1p(-u) / rate)
 
 
+MERGEPATH_ITEMS = 15     # outputs per thread of the merge-path baseline
+
+
+def mergepath_adversary_u32(n: int, vt: int = MERGEPATH_ITEMS) -> np.ndarray:
+    """Conflict-heavy permutation of 0..n-1 against a merge-path sort whose
+    threads merge vt outputs each (n = vt * 2^k); recipe in gen.c."""
+    out = _empty32(n)
+    tmp = _empty32(n)
+    if _get().mmsgen_mergepath_adversary_u32(out.ctypes.data_as(_u32p), tmp.ctypes.data_as(_u32p), out.size, vt):
+        raise ValueError("the merge-path adversary needs n = vt * 2^k")
+    return out
+
+
 def family(name: str, seed: int, n: int, swaps: int = 0) -> np.ndarray:
     """Keys of one named input family."""
     if name == "uniform":
@@ -153,6 +167,8 @@ def family(name: str, seed: int, n: int, swaps: int = 0) -> np.ndarray:
         return iota_u32(n)[::-1].copy()
     if name == "equal":
         return np.full(int(n), 0x5A5A5A5A, dtype=np.uint32)
+    if name == "mp_adversary":
+        return mergepath_adversary_u32(n)
     raise ValueError(f"unknown family {name!r}")
 
 

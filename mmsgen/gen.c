@@ -105,3 +105,66 @@ void mmsgen_unit_doubles(uint64_t seed, double* out, uint64_t count) {
     for (uint64_t i = 0; i < count; ++i)
         out[i] = (double)(sm64_next(&g) >> 11) * (1.0 / 9007199254740992.0);
 }
+
+/*
+ * Conflict-heavy input for a pairwise merge-path mergesort whose threads
+ * each merge vt consecutive outputs (§6.4's conflict-heavy inputs are built
+ * against one such sort; the paper gives no recipe, so this one is ours).
+ * n must be vt * 2^k.  Reading the sort's merge tree top-down, every merge
+ * of two runs of h keys has 2h/vt thread windows of vt outputs, counted from
+ * the start of the pair; in the first half of them a cycle of three windows
+ * takes vt, vt and 2 outputs from the first run (the rest of the third from
+ * the second run), in the second half the roles of the runs swap, and the
+ * last windows are adjusted so each run gets exactly h keys.  Threads of a
+ * cycle then read the first run at positions 2vt + 2 apart (32 for vt = 15)
+ * at every merge step, which for 32 banks is the same bank.  The sorted
+ * values 0..n-1 are split this way level by level down to runs of vt keys,
+ * which are laid out in descending order.
+ */
+static int mp_from_first(uint64_t pos, uint64_t pairlen, uint64_t vt) {
+    const uint64_t j = pos / vt, off = pos % vt;
+    const uint64_t threads = pairlen / vt;
+    const int heavy_first = j < threads / 2;
+    const int c = (int)(j % 3);
+    const int first = c < 2 ? 1 : (off < 2);
+    return heavy_first ? first : !first;
+}
+
+int mmsgen_mergepath_adversary_u32(uint32_t* out, uint32_t* tmp, uint64_t n, uint64_t vt) {
+    if (vt == 0 || n % vt) return -1;
+    uint64_t q = n / vt;
+    while (q > 1 && q % 2 == 0) q /= 2;
+    if (q != 1) return -1;
+    for (uint64_t i = 0; i < n; ++i) out[i] = (uint32_t)i;
+    for (uint64_t len = n; len > vt; len /= 2) {
+        const uint64_t h = len / 2;
+        for (uint64_t s = 0; s < n; s += len) {
+            const uint32_t* v = out + s;
+            /* how many of the pair's outputs the pattern gives the first run */
+            uint64_t na = 0;
+            for (uint64_t p = 0; p < len; ++p) na += (uint64_t)mp_from_first(p, len, vt);
+            /* balance: flip assignments from the end until na == h */
+            uint64_t fix_from = len;
+            uint64_t cnt = na;
+            while (cnt != h && fix_from > 0) {
+                --fix_from;
+                const int f = mp_from_first(fix_from, len, vt);
+                if (cnt > h && f) --cnt;
+                else if (cnt < h && !f) ++cnt;
+            }
+            uint64_t ia = 0, ib = h;
+            for (uint64_t p = 0; p < len; ++p) {
+                int f = mp_from_first(p, len, vt);
+                if (p >= fix_from) f = na > h ? 0 : 1;
+                if (f && ia < h) tmp[s + ia++] = v[p];
+                else tmp[s + ib++] = v[p];
+            }
+        }
+        memcpy(out, tmp, n * sizeof(uint32_t));
+    }
+    for (uint64_t s = 0; s < n; s += vt)
+        for (uint64_t a = s, b = s + vt - 1; a < b; ++a, --b) {
+            uint32_t t = out[a]; out[a] = out[b]; out[b] = t;
+        }
+    return 0;
+}

@@ -8,10 +8,10 @@ does, and fails loudly if it has not been built.
 from __future__ import annotations
 
 from . import _lib
-from ._lib import MMS_KEY_I32, MMS_PAIRS, MmsError, MmsPlan  # noqa: F401
+from ._lib import MMS_KEY_I32, MMS_KEY_I64, MMS_KEYS64, MMS_MERGEPATH, MMS_PAIRS, MmsError, MmsPlan  # noqa: F401
 from .server import Result, Server  # noqa: F401
 
-__all__ = ["sort", "sort_pairs", "partition", "copy", "plan", "workspace_bytes", "MmsError",
+__all__ = ["sort", "sort_pairs", "sort64", "sort_pairs64", "sort_mergepath", "partition", "copy", "plan", "workspace_bytes", "MmsError",
            "timing_enable", "timing_reset", "timing_read", "segmented_sort", "segmented_workspace_bytes",
            "set_tuning", "get_tuning", "Server", "Result"]
 
@@ -38,21 +38,24 @@ def _check_u32(t, name):
         raise ValueError(f"{name} must be contiguous")
 
 
-def plan(n: int, pairs: bool = False, i32: bool = False) -> MmsPlan:
+def plan(n: int, pairs: bool = False, i32: bool = False, keys64: bool = False,
+         mergepath: bool = False) -> MmsPlan:
     """Tile size, fan-out, rounds, passes and workspace for a sort of n elements."""
     p = MmsPlan()
-    flags = (MMS_PAIRS if pairs else 0) | (MMS_KEY_I32 if i32 else 0)
+    flags = ((MMS_PAIRS if pairs else 0) | (MMS_KEY_I32 if i32 else 0) | (MMS_KEYS64 if keys64 else 0)
+             | (MMS_MERGEPATH if mergepath else 0))
     _lib.check(_lib.lib().mms_plan(int(n), flags, p))
     return p
 
 
-def workspace_bytes(n: int, pairs: bool = False) -> int:
-    return int(_lib.lib().mms_workspace_bytes(int(n), MMS_PAIRS if pairs else 0))
+def workspace_bytes(n: int, pairs: bool = False, keys64: bool = False) -> int:
+    flags = (MMS_PAIRS if pairs else 0) | (MMS_KEYS64 if keys64 else 0)
+    return int(_lib.lib().mms_workspace_bytes(int(n), flags))
 
 
-def _workspace(n, pairs, device, workspace):
+def _workspace(n, pairs, device, workspace, keys64=False):
     torch = _torch()
-    need = workspace_bytes(n, pairs)
+    need = workspace_bytes(n, pairs, keys64)
     if workspace is not None:
         if workspace.numel() * workspace.element_size() < need:
             raise ValueError(f"workspace needs {need} bytes")
@@ -104,6 +107,85 @@ def sort_pairs(keys, values, out_keys=None, out_values=None, i32: bool | None = 
     _lib.check(_lib.lib().mms_sort_pairs_u32(
         keys.data_ptr(), values.data_ptr(), out_keys.data_ptr(), out_values.data_ptr(), n,
         ws.data_ptr() if ws is not None else None, need, MMS_KEY_I32 if i32 else 0,
+        _stream_ptr(stream)))
+    return out_keys, out_values
+
+
+def sort_mergepath(keys, out=None, i32: bool | None = None, workspace=None, stream=None):
+    """The merge-path baseline (pairwise, per-thread serial merges): sorts a
+    1-D int32/uint32 device tensor ascending like :func:`sort`."""
+    torch = _torch()
+    _check_u32(keys, "keys")
+    if i32 is None:
+        i32 = keys.dtype == torch.int32
+    n = keys.numel()
+    if out is None:
+        out = torch.empty_like(keys)
+    _check_u32(out, "out")
+    if out.numel() != n:
+        raise ValueError("out has the wrong size")
+    need = int(_lib.lib().mms_workspace_bytes(n, MMS_MERGEPATH))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=keys.device)
+    elif workspace.numel() * workspace.element_size() < need:
+        raise ValueError(f"workspace needs {need} bytes")
+    _lib.check(_lib.lib().mms_sort_mergepath_u32(keys.data_ptr(), out.data_ptr(), n, workspace.data_ptr(), need,
+                                                 MMS_KEY_I32 if i32 else 0, _stream_ptr(stream)))
+    return out
+
+
+def _check_u64(t, name):
+    torch = _torch()
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype not in (torch.int64, torch.uint64):
+        raise ValueError(f"{name} must be int64/uint64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def sort64(keys, out=None, i64: bool | None = None, workspace=None, stream=None):
+    """Sort a 1-D int64/uint64 device tensor ascending; returns ``out``.
+
+    int64 tensors sort in signed order, uint64 in unsigned order, unless
+    ``i64`` says otherwise.  ``out`` may be ``keys`` itself (in place).
+    """
+    torch = _torch()
+    _check_u64(keys, "keys")
+    if i64 is None:
+        i64 = keys.dtype == torch.int64
+    n = keys.numel()
+    if out is None:
+        out = torch.empty_like(keys)
+    _check_u64(out, "out")
+    if out.numel() != n:
+        raise ValueError("out has the wrong size")
+    ws, need = _workspace(n, False, keys.device, workspace, keys64=True)
+    _lib.check(_lib.lib().mms_sort_u64(keys.data_ptr(), out.data_ptr(), n,
+                                       ws.data_ptr() if ws is not None else None, need,
+                                       MMS_KEY_I64 if i64 else 0, _stream_ptr(stream)))
+    return out
+
+
+def sort_pairs64(keys, values, out_keys=None, out_values=None, i64: bool | None = None,
+                 workspace=None, stream=None):
+    """Stable sort of (64-bit key, 64-bit value) pairs by key; returns (out_keys, out_values)."""
+    torch = _torch()
+    _check_u64(keys, "keys")
+    _check_u64(values, "values")
+    if i64 is None:
+        i64 = keys.dtype == torch.int64
+    n = keys.numel()
+    if values.numel() != n:
+        raise ValueError("keys and values differ in size")
+    if out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if out_values is None:
+        out_values = torch.empty_like(values)
+    ws, need = _workspace(n, True, keys.device, workspace, keys64=True)
+    _lib.check(_lib.lib().mms_sort_pairs_u64(
+        keys.data_ptr(), values.data_ptr(), out_keys.data_ptr(), out_values.data_ptr(), n,
+        ws.data_ptr() if ws is not None else None, need, MMS_KEY_I64 if i64 else 0,
         _stream_ptr(stream)))
     return out_keys, out_values
 

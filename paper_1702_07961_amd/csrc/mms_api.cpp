@@ -110,7 +110,7 @@ Tune env_default() {
 
 bool valid_tune(uint32_t K, uint32_t Tout, int variant, int base) {
     return K >= 2 && K <= mms::kMaxFanout && (K & (K - 1)) == 0 && Tout >= 1024 && Tout <= mms::kToutKeys &&
-           Tout % 256 == 0 && variant >= 0 && variant <= 3 && base >= 0 && base < mms::kBaseShapes;
+           Tout % 256 == 0 && variant >= 0 && variant <= 4 && base >= 0 && base < mms::kBaseShapes;
 }
 
 // Entries of one kind (keys-only or key-value) ordered by max_log2_n; a sort
@@ -332,11 +332,12 @@ bool overlaps(const void* a, uint64_t abytes, const void* b, uint64_t bbytes) {
 // a and b either coincide exactly or are disjoint
 bool same_or_disjoint(const void* a, const void* b, uint64_t bytes) { return a == b || !overlaps(a, bytes, b, bytes); }
 
-int check_buffers(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint64_t n, void* ws,
-                  uint64_t ws_need, size_t ws_bytes) {
+// esize: bytes per key (and per value)
+int check_buffers(const void* kin, const void* vin, void* kout, void* vout, uint64_t n, void* ws, uint64_t ws_need,
+                  size_t ws_bytes, uint64_t esize = 4) {
     const bool pairs = vin != nullptr;
     if (!kin || !kout || (pairs && !vout)) return fail(MMS_EINVAL, "null data pointer");
-    const uint64_t bytes = n * 4;
+    const uint64_t bytes = n * esize;
     if (!same_or_disjoint(kin, kout, bytes)) return fail(MMS_EINVAL, "keys in/out partially overlap");
     if (pairs) {
         if (!same_or_disjoint(vin, vout, bytes)) return fail(MMS_EINVAL, "values in/out partially overlap");
@@ -382,18 +383,152 @@ int sort_impl(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t
                      (hipStream_t)stream);
 }
 
+// ---- 64-bit keys (§6.3 also sorts 8-byte integers) ----------------------------
+// Base tiles of kT64Keys keys or kT64Pairs pairs, merge tiles of
+// kTout64Keys / kTout64Pairs, fan-out 16 (MMS64_FANOUT overrides it for
+// experiments: 2, 4, 8 or 16).
+uint32_t fanout64() {
+    const char* e = getenv("MMS64_FANOUT");
+    const uint32_t v = e ? (uint32_t)atoi(e) : 16u;
+    return (v >= 2 && v <= mms::kMaxFanout && (v & (v - 1)) == 0) ? v : 16u;
+}
+
+struct Plan64 {
+    uint64_t n;
+    bool pairs;
+    uint32_t T, K, Tout, rounds;
+    uint64_t max_tiles, off_vals, off_table, ws_bytes;
+};
+
+Plan64 make_plan64(uint64_t n, bool pairs) {
+    Plan64 p{};
+    p.n = n;
+    p.pairs = pairs;
+    p.T = pairs ? mms::kT64Pairs : mms::kT64Keys;
+    p.K = fanout64();
+    p.Tout = pairs ? mms::kTout64Pairs : mms::kTout64Keys;
+    p.rounds = rounds_for(n, p.T, p.K);
+    uint64_t L = p.T;
+    for (uint32_t r = 0; r < p.rounds; ++r, L *= p.K)
+        p.max_tiles = std::max<uint64_t>(p.max_tiles, mms::round_geom(n, L, p.K, p.Tout).tiles);
+    p.off_vals = align_up(n * 8);
+    p.off_table = p.off_vals + (pairs ? align_up(n * 8) : 0);
+    p.ws_bytes = p.rounds ? p.off_table + align_up((p.max_tiles + 1) * p.K * 4) : 0;
+    return p;
+}
+
+int sort64_impl(const uint64_t* kin, const uint64_t* vin, uint64_t* kout, uint64_t* vout, uint64_t n, void* ws,
+                size_t ws_bytes, uint32_t flags, hipStream_t s) {
+    const bool pairs = vin != nullptr;
+    if (flags & ~MMS_KEY_I64) return fail(MMS_EINVAL, "unknown flags 0x%x for a 64-bit sort", flags);
+    if (n == 0) return MMS_OK;
+    if (n >= (1ull << 32)) return fail(MMS_EINVAL, "n = %llu exceeds 2^32-1", (unsigned long long)n);
+    const Plan64 p = make_plan64(n, pairs);
+    int rc = check_buffers(kin, vin, kout, vout, n, ws, p.ws_bytes, ws_bytes, 8);
+    if (rc) return rc;
+    uint8_t* wsb = (uint8_t*)ws;
+    const mms::Bufs64 b{kin, vin, kout, vout, (uint64_t*)wsb, pairs ? (uint64_t*)(wsb + p.off_vals) : nullptr};
+    uint32_t* table = p.rounds ? (uint32_t*)(wsb + p.off_table) : nullptr;
+    const uint64_t flip = (flags & MMS_KEY_I64) ? 0x8000000000000000ull : 0ull;
+    hipError_t e;
+    {
+        // pass i writes the output when R - i is even, so pass R lands there
+        const mms::Phase64 base{n, (p.rounds % 2 == 0) ? 1u : 0u, p.rounds == 0 ? 1u : 0u, (n + p.T - 1) / p.T};
+        Timed tm(MMS_KERNEL_TILE_SORT, s);
+        e = mms::launch_tile_sort64(pairs, base, b, flip, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "tile sort launch");
+    uint64_t L = p.T;
+    for (uint32_t r = 0; r < p.rounds; ++r, L *= p.K) {
+        const mms::RoundGeom g = mms::round_geom(n, L, p.K, p.Tout);
+        const mms::Phase64 ph{n, ((p.rounds - r - 1) % 2 == 0) ? 1u : 0u, r + 1 == p.rounds ? 1u : 0u, g.tiles};
+        const mms::RoundArgs ra{L, p.K, p.Tout, (L * p.K + p.Tout - 1) / p.Tout};
+        {
+            Timed tm(MMS_KERNEL_PARTITION, s);
+            e = mms::launch_corank_tiles64(ph, b, ra, table, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "partition launch");
+        {
+            Timed tm(MMS_KERNEL_MERGE, s);
+            e = mms::launch_merge64(pairs, ph, b, ra, table, flip, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "merge launch");
+    }
+    return MMS_OK;
+}
+
+// ---- merge-path baseline -----------------------------------------------------------
+// A block sort of kMergePathTile-key tiles, then ceil(log2(tiles)) pairwise
+// merge passes, each a partition launch and a merge launch; buffers
+// ping-pong between the output and the workspace, which also holds the
+// split table.
+struct PlanMP {
+    uint32_t rounds;
+    uint64_t max_tiles, off_table, ws_bytes;
+};
+
+PlanMP make_plan_mp(uint64_t n) {
+    PlanMP p{};
+    p.rounds = rounds_for(n, mms::kMergePathTile, 2);
+    uint64_t L = mms::kMergePathTile;
+    for (uint32_t r = 0; r < p.rounds; ++r, L *= 2)
+        p.max_tiles = std::max<uint64_t>(p.max_tiles, mms::round_geom(n, L, 2, mms::kMergePathTile).tiles);
+    p.off_table = align_up(n * 4);
+    p.ws_bytes = p.rounds ? p.off_table + align_up((p.max_tiles + 1) * 4) : 0;
+    return p;
+}
+
+int mergepath_impl(const uint32_t* in, uint32_t* out, uint64_t n, void* ws, size_t ws_bytes, uint32_t flags,
+                   hipStream_t s) {
+    if (flags & ~MMS_KEY_I32) return fail(MMS_EINVAL, "unknown flags 0x%x for the merge-path sort", flags);
+    if (n == 0) return MMS_OK;
+    if (n >= (1ull << 32)) return fail(MMS_EINVAL, "n = %llu exceeds 2^32-1", (unsigned long long)n);
+    const PlanMP p = make_plan_mp(n);
+    int rc = check_buffers(in, nullptr, out, nullptr, n, ws, p.ws_bytes, ws_bytes);
+    if (rc) return rc;
+    uint32_t* wk = (uint32_t*)ws;
+    uint32_t* split = p.rounds ? (uint32_t*)((uint8_t*)ws + p.off_table) : nullptr;
+    const uint32_t flip = (flags & MMS_KEY_I32) ? 0x80000000u : 0u;
+    // pass i writes the output when R - i is even, so pass R lands there
+    auto buf = [&](uint32_t pass) { return ((p.rounds - pass) % 2 == 0) ? out : wk; };
+    hipError_t e;
+    {
+        Timed tm(MMS_KERNEL_TILE_SORT, s);
+        e = mms::launch_mp_blocksort(in, buf(0), n, flip, p.rounds == 0 ? flip : 0u, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "block sort launch");
+    uint64_t L = mms::kMergePathTile;
+    for (uint32_t r = 0; r < p.rounds; ++r, L *= 2) {
+        const uint32_t* src = buf(r);
+        uint32_t* dst = buf(r + 1);
+        {
+            Timed tm(MMS_KERNEL_PARTITION, s);
+            e = mms::launch_mp_partition(src, n, L, split, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "partition launch");
+        {
+            Timed tm(MMS_KERNEL_MERGE, s);
+            e = mms::launch_mp_merge(src, dst, n, L, split, r + 1 == p.rounds ? flip : 0u, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "merge launch");
+    }
+    return MMS_OK;
+}
+
 // ---- segmented batch -----------------------------------------------------------
 // Every segment is sorted as its own plain sort; each phase's tiles of all
 // segments form one task list, so the batch runs one launch per kernel and
 // phase.  The workspace mirrors the arrays: segment s uses
-// ws[h_offsets[s] .. h_offsets[s+1]) for keys (and the values region likewise).
+// ws[h_offsets[s] .. h_offsets[s+1]) for keys (and the values region likewise),
+// followed by the partition table and the batch metadata (the SegDesc table,
+// then the task lists phase after phase).
 struct SegPlan {
     bool pairs;
     uint64_t total;                    // h_offsets[num_segs]
     std::vector<uint64_t> seg_off;     // non-empty segments
     std::vector<uint64_t> seg_n;
     BatchTasks bt;
-    uint64_t off_vals, off_table, ws_bytes;
+    uint64_t off_vals, off_table, off_meta, seg_bytes, meta_bytes, ws_bytes;
 };
 
 int make_seg_plan(const uint64_t* off, uint64_t ns, uint32_t flags, SegPlan& sp) {
@@ -416,17 +551,24 @@ int make_seg_plan(const uint64_t* off, uint64_t ns, uint32_t flags, SegPlan& sp)
                       sp.bt);
     sp.off_vals = align_up(sp.total * 4);
     sp.off_table = sp.off_vals + (sp.pairs ? align_up(sp.total * 4) : 0);
-    sp.ws_bytes = sp.off_table + sp.bt.table_bytes();
+    sp.off_meta = sp.off_table + sp.bt.table_bytes();
+    sp.seg_bytes = align_up(sp.seg_n.size() * sizeof(mms::SegDesc));
+    sp.meta_bytes = align_up(sp.seg_bytes + sp.bt.ntasks * sizeof(mms::TileTask));
+    sp.ws_bytes = sp.off_meta + sp.meta_bytes;
     return MMS_OK;
 }
 
-// A captured batch: SegDesc table and task lists in device memory owned by
-// the library, and the instantiated graph of all launches, keyed by
-// offsets, pointers and tuning.
+// A captured batch, keyed by offsets, pointers and tuning: the host image of
+// its metadata in pinned host memory the library owns (uploaded into the
+// caller's workspace by an asynchronous copy on the caller's stream before
+// every launch), and the instantiated graph of all kernel launches.  The
+// event is recorded after each launch, so an entry is torn down only after
+// the last work that reads its image or runs its graph has finished.
 struct SegEntry {
     std::string key;
     SegPlan plan;
-    void* d_meta = nullptr;
+    void* h_meta = nullptr;
+    hipEvent_t last_use = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
 };
@@ -436,12 +578,17 @@ std::list<SegEntry> g_seg_cache;   // most recent first
 constexpr size_t kSegCacheMax = 8;
 
 void drop_entry(SegEntry& e) {
+    if (e.last_use) {
+        (void)hipEventSynchronize(e.last_use);
+        (void)hipEventDestroy(e.last_use);
+    }
     if (e.exec) (void)hipGraphExecDestroy(e.exec);
     if (e.graph) (void)hipGraphDestroy(e.graph);
-    if (e.d_meta) (void)hipFree(e.d_meta);
+    if (e.h_meta) (void)hipHostFree(e.h_meta);
+    e.last_use = nullptr;
     e.exec = nullptr;
     e.graph = nullptr;
-    e.d_meta = nullptr;
+    e.h_meta = nullptr;
 }
 
 std::string seg_key(const uint64_t* off, uint64_t ns, uint32_t flags, const void* const* ptrs, int nptr,
@@ -489,26 +636,30 @@ int segmented_impl(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uin
         uint8_t* wsb = (uint8_t*)ws;
         uint32_t* ws_k = (uint32_t*)wsb;
         uint32_t* ws_v = pairs ? (uint32_t*)(wsb + p.off_vals) : nullptr;
-        // host image of the device metadata: SegDesc table, then the tasks
-        const uint64_t seg_bytes = align_up(p.seg_n.size() * sizeof(mms::SegDesc));
-        std::vector<uint8_t> img(seg_bytes + p.bt.ntasks * sizeof(mms::TileTask));
-        mms::SegDesc* sd = (mms::SegDesc*)img.data();
+        // host image of the metadata: SegDesc table, then the tasks
+        hipError_t he = hipHostMalloc(&e.h_meta, p.meta_bytes, hipHostMallocDefault);
+        if (he != hipSuccess) {
+            e.h_meta = nullptr;
+            return fail(MMS_ENOMEM, "pinned staging of the batch metadata: %s", hipGetErrorString(he));
+        }
+        he = hipEventCreateWithFlags(&e.last_use, hipEventDisableTiming);
+        if (he != hipSuccess) {
+            e.last_use = nullptr;
+            drop_entry(e);
+            return hip_fail(he, "batch event");
+        }
+        uint8_t* img = (uint8_t*)e.h_meta;
+        memset(img, 0, p.meta_bytes);
+        mms::SegDesc* sd = (mms::SegDesc*)img;
         for (size_t i = 0; i < p.seg_n.size(); ++i) {
             const uint64_t o = p.seg_off[i];
             sd[i] = mms::SegDesc{kin + o, pairs ? vin + o : nullptr, kout + o, pairs ? vout + o : nullptr,
                                  ws_k + o, pairs ? ws_v + o : nullptr, p.seg_n[i], 0};
         }
-        size_t at = seg_bytes;
+        size_t at = p.seg_bytes;
         for (auto& v : p.bt.phases) {
-            if (!v.empty()) memcpy(img.data() + at, v.data(), v.size() * sizeof(mms::TileTask));
+            if (!v.empty()) memcpy(img + at, v.data(), v.size() * sizeof(mms::TileTask));
             at += v.size() * sizeof(mms::TileTask);
-        }
-        hipError_t he = hipMalloc(&e.d_meta, img.size());
-        if (he != hipSuccess) return fail(MMS_ENOMEM, "task list allocation: %s", hipGetErrorString(he));
-        he = hipMemcpy(e.d_meta, img.data(), img.size(), hipMemcpyHostToDevice);
-        if (he != hipSuccess) {
-            drop_entry(e);
-            return hip_fail(he, "task list upload");
         }
         g_seg_cache.push_front(std::move(e));
         while (g_seg_cache.size() > kSegCacheMax) {
@@ -522,12 +673,22 @@ int segmented_impl(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uin
     }
     SegEntry& e = *it;
     const SegPlan& p = e.plan;
-    const mms::SegDesc* d_segs = (const mms::SegDesc*)e.d_meta;
-    const mms::TileTask* d_tasks =
-        (const mms::TileTask*)((uint8_t*)e.d_meta + align_up(p.seg_n.size() * sizeof(mms::SegDesc)));
+    uint8_t* d_meta = (uint8_t*)ws + p.off_meta;
+    const mms::SegDesc* d_segs = (const mms::SegDesc*)d_meta;
+    const mms::TileTask* d_tasks = (const mms::TileTask*)(d_meta + p.seg_bytes);
     uint32_t* table = (uint32_t*)((uint8_t*)ws + p.off_table);
     const uint32_t flip = (flags & MMS_KEY_I32) ? 0x80000000u : 0u;
-    if (!seg_graph_enabled()) return run_batch(p.bt, d_segs, d_tasks, table, flip, s);
+    // the metadata goes into the caller's workspace on the caller's stream,
+    // ahead of the launches that read it (every call: the caller may have
+    // used the workspace for something else in between)
+    hipError_t ue = hipMemcpyAsync(d_meta, e.h_meta, p.meta_bytes, hipMemcpyHostToDevice, s);
+    if (ue != hipSuccess) return hip_fail(ue, "batch metadata upload");
+    if (!seg_graph_enabled()) {
+        rc = run_batch(p.bt, d_segs, d_tasks, table, flip, s);
+        const hipError_t ee = hipEventRecord(e.last_use, s);
+        if (rc) return rc;
+        return ee == hipSuccess ? MMS_OK : hip_fail(ee, "batch event");
+    }
 
     if (!e.exec) {
         hipStream_t cap = nullptr;
@@ -562,6 +723,8 @@ int segmented_impl(const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uin
         he = hipGraphLaunch(e.exec, s);
     }
     if (he != hipSuccess) return hip_fail(he, "graph launch");
+    he = hipEventRecord(e.last_use, s);
+    if (he != hipSuccess) return hip_fail(he, "batch event");
     return MMS_OK;
 }
 
@@ -575,8 +738,37 @@ int mms_version(void) { return 200; }
 
 int mms_plan(uint64_t n, uint32_t flags, mms_plan_t* out) {
     if (!out) return fail(MMS_EINVAL, "null plan pointer");
-    if (flags & ~(MMS_KEY_I32 | MMS_PAIRS)) return fail(MMS_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(MMS_KEY_I32 | MMS_PAIRS | MMS_KEY_I64 | MMS_KEYS64 | MMS_MERGEPATH))
+        return fail(MMS_EINVAL, "unknown flags 0x%x", flags);
     if (n >= (1ull << 32)) return fail(MMS_EINVAL, "n = %llu exceeds 2^32-1", (unsigned long long)n);
+    if (flags & MMS_MERGEPATH) {
+        if (flags & (MMS_PAIRS | MMS_KEYS64 | MMS_KEY_I64))
+            return fail(MMS_EINVAL, "the merge-path sort takes 32-bit keys only");
+        const PlanMP p = make_plan_mp(n);
+        out->n = n;
+        out->flags = flags;
+        out->tile = mms::kMergePathTile;
+        out->lanes_per_tile = mms::kMergePathThreads;
+        out->fanout = 2;
+        out->merge_tile = mms::kMergePathTile;
+        out->rounds = n ? p.rounds : 0;
+        out->passes = n ? 1 + p.rounds : 0;
+        out->workspace_bytes = p.ws_bytes;
+        return MMS_OK;
+    }
+    if (flags & MMS_KEYS64) {
+        const Plan64 p = make_plan64(n, (flags & MMS_PAIRS) != 0);
+        out->n = n;
+        out->flags = flags;
+        out->tile = p.T;
+        out->lanes_per_tile = (p.pairs ? 4 : 8) * 64;
+        out->fanout = p.K;
+        out->merge_tile = p.Tout;
+        out->rounds = n ? p.rounds : 0;
+        out->passes = n ? 1 + p.rounds : 0;
+        out->workspace_bytes = p.ws_bytes;
+        return MMS_OK;
+    }
     const Plan p = make_plan(n, flags);
     out->n = n;
     out->flags = flags;
@@ -592,7 +784,25 @@ int mms_plan(uint64_t n, uint32_t flags, mms_plan_t* out) {
 
 size_t mms_workspace_bytes(uint64_t n, uint32_t flags) {
     if (n == 0 || n >= (1ull << 32)) return 0;
+    if (flags & MMS_MERGEPATH) return (size_t)make_plan_mp(n).ws_bytes;
+    if (flags & MMS_KEYS64) return (size_t)make_plan64(n, (flags & MMS_PAIRS) != 0).ws_bytes;
     return (size_t)make_plan(n, flags).ws_bytes;
+}
+
+int mms_sort_mergepath_u32(const uint32_t* d_in, uint32_t* d_out, uint64_t n, void* d_ws, size_t ws_bytes,
+                           uint32_t flags, void* stream) {
+    return mergepath_impl(d_in, d_out, n, d_ws, ws_bytes, flags, (hipStream_t)stream);
+}
+
+int mms_sort_u64(const uint64_t* d_in, uint64_t* d_out, uint64_t n, void* d_ws, size_t ws_bytes, uint32_t flags,
+                 void* stream) {
+    return sort64_impl(d_in, nullptr, d_out, nullptr, n, d_ws, ws_bytes, flags, (hipStream_t)stream);
+}
+
+int mms_sort_pairs_u64(const uint64_t* d_kin, const uint64_t* d_vin, uint64_t* d_kout, uint64_t* d_vout,
+                       uint64_t n, void* d_ws, size_t ws_bytes, uint32_t flags, void* stream) {
+    if (n && !d_vin) return fail(MMS_EINVAL, "null value pointer");
+    return sort64_impl(d_kin, d_vin, d_kout, d_vout, n, d_ws, ws_bytes, flags, (hipStream_t)stream);
 }
 
 int mms_sort_u32(const uint32_t* d_in, uint32_t* d_out, uint64_t n, void* d_ws, size_t ws_bytes, uint32_t flags,

@@ -127,8 +127,8 @@ __device__ __forceinline__ Elem<true> shfl_xor(const Elem<true>& e, int m) {
 // lanes for the rest).  Result layout is "blocked": lane l holds positions
 // l*E .. l*E+E-1 of the wave's sorted run.
 // ---------------------------------------------------------------------------
-template <int E, bool P>
-__device__ __forceinline__ void wave_sort_blocked(Elem<P> (&r)[E], int lane) {
+template <int E, class El>
+__device__ __forceinline__ void wave_sort_blocked(El (&r)[E], int lane) {
 #pragma unroll
     for (int s = 1; s < E; s <<= 1) {
 #pragma unroll
@@ -145,7 +145,7 @@ __device__ __forceinline__ void wave_sort_blocked(Elem<P> (&r)[E], int lane) {
     for (int sl = 1; sl < kWave; sl <<= 1) {
         // mirror stage: (lane, e) meets (lane ^ (2sl-1), E-1-e)
         const bool lower = (lane & sl) == 0;
-        Elem<P> t[E];
+        El t[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) t[e] = pick(r[e], shfl_xor(r[E - 1 - e], 2 * sl - 1), lower);
 #pragma unroll
@@ -165,12 +165,31 @@ __device__ __forceinline__ void wave_sort_blocked(Elem<P> (&r)[E], int lane) {
     }
 }
 
+// The in-wave tail of a bitonic merge in the blocked layout: lane distances
+// 32 .. 1, then register distances (after the cross-wave stages of a
+// workgroup-wide merge).
+template <int E, class El>
+__device__ __forceinline__ void wave_merge_tail(El (&r)[E], int lane) {
+#pragma unroll
+    for (int dl = kWave / 2; dl >= 1; dl >>= 1) {
+        const bool lo = (lane & dl) == 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) r[e] = pick(r[e], shfl_xor(r[e], dl), lo);
+    }
+#pragma unroll
+    for (int d = E / 2; d >= 1; d >>= 1) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if ((e & d) == 0) cex(r[e], r[e | d]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Bitonic merge of 64*EM elements held "striped" (lane l, register e holds
 // index e*64 + l): register distances first, then lane distances 32..1.
 // ---------------------------------------------------------------------------
-template <int EM, bool P>
-__device__ __forceinline__ void bitonic_merge_striped(Elem<P> (&m)[EM], int lane) {
+template <int EM, class El>
+__device__ __forceinline__ void bitonic_merge_striped(El (&m)[EM], int lane) {
 #pragma unroll
     for (int d = EM / 2; d >= 1; d >>= 1) {
 #pragma unroll
@@ -185,14 +204,20 @@ __device__ __forceinline__ void bitonic_merge_striped(Elem<P> (&m)[EM], int lane
     }
 }
 
-// LDS element access: tags are LDS positions (the pass's stable order)
-template <bool P> __device__ __forceinline__ Elem<P> lds_get(const uint32_t* Xk, const uint32_t* Xv, uint32_t i);
-template <> __device__ __forceinline__ Elem<false> lds_get<false>(const uint32_t* Xk, const uint32_t*, uint32_t i) {
-    return {Xk[i]};
-}
-template <> __device__ __forceinline__ Elem<true> lds_get<true>(const uint32_t* Xk, const uint32_t* Xv, uint32_t i) {
-    return {Xk[i], i, Xv[i]};
-}
+// LDS views of a merge buffer: key(i) is the key at LDS position i, get(i)
+// the whole element, whose tag is its LDS position (the pass's stable
+// order), put(i, e) stores an element (a view is also a merge-level sink).
+struct LdsKV32 {
+    using El = Elem<true>;
+    uint32_t* k;
+    uint32_t* v;
+    __device__ __forceinline__ uint32_t key(uint32_t i) const { return k[i]; }
+    __device__ __forceinline__ El get(uint32_t i) const { return {k[i], i, v[i]}; }
+    __device__ __forceinline__ void put(uint32_t i, const El& e) const {
+        k[i] = e.k;
+        v[i] = e.v;
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Merge-path split inside LDS: the number p of elements of A = X[aA, aA+la)
@@ -227,15 +252,33 @@ __device__ __forceinline__ uint32_t lds_corank2(const uint32_t* Xk, uint32_t aA,
     return lo;
 }
 
-// Output sinks for a merged range
-template <bool P> struct LdsSink {
-    uint32_t* k;
-    uint32_t* v;
-    __device__ __forceinline__ void put(uint32_t i, const Elem<P>& e) const {
-        k[i] = e.k;
-        if constexpr (P) v[i] = e.v;
+// lds_corank2 over any LDS view (keys compared alone, A first on ties, which
+// is the stable order of the two runs).  For 64-bit keys the probes at an odd
+// stride also fall on distinct bank pairs: 32 lanes are served per cycle and
+// lane l covers words 2(c + l*step) and 2(c + l*step) + 1.
+template <class View>
+__device__ __forceinline__ uint32_t lds_corank2_view(const View& X, uint32_t aA, uint32_t la, uint32_t aB,
+                                                     uint32_t lb, uint32_t d, int lane) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(d > lb ? d - lb : 0u));
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)min(d, la));
+    while (lo < hi) {
+        const uint32_t R = hi - lo;
+        const uint32_t step = ((R + 127u) >> 7) | 1u;
+        const uint32_t m0 = lo + (uint32_t)lane * step;
+        const uint32_t m1 = m0 + 64u * step;
+        const bool v0 = m0 < hi, v1 = m1 < hi;
+        const uint32_t c0 = v0 ? m0 : hi - 1u, c1 = v1 ? m1 : hi - 1u;
+        const bool p0 = v0 && X.key(aA + c0) <= X.key(aB + d - 1u - c0);
+        const bool p1 = v1 && X.key(aA + c1) <= X.key(aB + d - 1u - c1);
+        const uint32_t t = (uint32_t)__popcll(__ballot(p0)) + (uint32_t)__popcll(__ballot(p1));
+        const uint32_t nvalid = (uint32_t)__popcll(__ballot(v0)) + (uint32_t)__popcll(__ballot(v1));
+        const uint32_t nlo = t > 0 ? lo + (t - 1u) * step + 1u : lo;
+        const uint32_t nhi = t < nvalid ? lo + t * step : hi;
+        lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)nlo);
+        hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)nhi);
     }
-};
+    return lo;
+}
 // Writes to memory, undoing the signed-key mapping; positions >= lim are
 // dropped (they hold the sentinels of a ragged tile).
 template <bool P> struct GlobalSinkLim {
@@ -257,39 +300,39 @@ template <bool P> struct GlobalSinkLim {
 // keeps the smaller of each opposing pair — the N smallest remaining
 // elements, as a bitonic sequence — and sorts them with a bitonic merge.
 // The number u of A elements kept advances the wave-uniform cursors.  Reads
-// are 64 consecutive words per instruction; writes likewise.
+// are 64 consecutive elements per instruction; writes likewise.
 // Positions past the end of A or B read as sentinels; with keys alone a
 // sentinel may stand in for an equal real maximum key, which leaves the
-// output values unchanged.
+// output values unchanged.  X is an LDS view (key / get / put).
 // ---------------------------------------------------------------------------
-template <int EM, bool P, class Sink>
-__device__ __forceinline__ void merge_pair_range(const uint32_t* Xk, const uint32_t* Xv, uint32_t aA, uint32_t la,
-                                                 uint32_t aB, uint32_t lb, uint32_t d0, uint32_t d1,
-                                                 const Sink& out, uint32_t out_base, int lane) {
+template <int EM, class View, class Sink>
+__device__ __forceinline__ void merge_pair_range(const View& X, uint32_t aA, uint32_t la, uint32_t aB, uint32_t lb,
+                                                 uint32_t d0, uint32_t d1, const Sink& out, uint32_t out_base,
+                                                 int lane) {
+    using El = typename View::El;
     constexpr uint32_t N = (uint32_t)kWave * EM;
     if (la == 0 || lb == 0) {   // one run is empty: the other is already in order
         const uint32_t a0 = lb == 0 ? aA : aB;
-        for (uint32_t k = d0 + (uint32_t)lane; k < d1; k += (uint32_t)kWave)
-            out.put(out_base + k, lds_get<P>(Xk, Xv, a0 + k));
+        for (uint32_t k = d0 + (uint32_t)lane; k < d1; k += (uint32_t)kWave) out.put(out_base + k, X.get(a0 + k));
         return;
     }
-    uint32_t p = lds_corank2(Xk, aA, la, aB, lb, d0, lane);
+    uint32_t p = lds_corank2_view(X, aA, la, aB, lb, d0, lane);
     uint32_t q = d0 - p;
     for (uint32_t o = d0; o < d1; o += N) {
-        Elem<P> m[EM];
+        El m[EM];
         uint32_t u = 0;
 #pragma unroll
         for (int e = 0; e < EM; ++e) {
             const uint32_t k = (uint32_t)e * kWave + (uint32_t)lane;
             const uint32_t ia = p + k;
             const uint32_t jb = q + (N - 1u - k);
-            const Elem<P> a = ia < la ? lds_get<P>(Xk, Xv, aA + ia) : Elem<P>::sentinel();
-            const Elem<P> b = jb < lb ? lds_get<P>(Xk, Xv, aB + jb) : Elem<P>::sentinel();
+            const El a = ia < la ? X.get(aA + ia) : El::sentinel();
+            const El b = jb < lb ? X.get(aB + jb) : El::sentinel();
             const bool take_a = !before(b, a);
             m[e] = take_a ? a : b;
             u += (uint32_t)__popcll(__ballot(take_a));
         }
-        bitonic_merge_striped<EM, P>(m, lane);
+        bitonic_merge_striped<EM>(m, lane);
         const uint32_t cnt = min(N, d1 - o);
 #pragma unroll
         for (int e = 0; e < EM; ++e) {
@@ -307,10 +350,9 @@ __device__ __forceinline__ void merge_pair_range(const uint32_t* Xk, const uint3
 // [w*total/nw, (w+1)*total/nw) of the whole level, so the work is balanced
 // whatever the segment lengths.
 // ---------------------------------------------------------------------------
-template <int EM, bool P, class Sink>
-__device__ __forceinline__ void merge_level(const uint32_t* Xk, const uint32_t* Xv, const uint32_t* seg0,
-                                            uint32_t nseg0, uint32_t lvl, uint32_t total, const Sink& out,
-                                            int wave, int nwaves, int lane) {
+template <int EM, class View, class Sink>
+__device__ __forceinline__ void merge_level(const View& X, const uint32_t* seg0, uint32_t nseg0, uint32_t lvl,
+                                            uint32_t total, const Sink& out, int wave, int nwaves, int lane) {
     // total < 2^20 here, so the 32-bit products cannot overflow
     const uint32_t o0 = total * (uint32_t)wave / (uint32_t)nwaves;
     const uint32_t o1 = total * (uint32_t)(wave + 1) / (uint32_t)nwaves;
@@ -322,7 +364,7 @@ __device__ __forceinline__ void merge_level(const uint32_t* Xk, const uint32_t* 
         const uint32_t s2 = seg0[min((2u * i + 2u) << lvl, nseg0)];
         const uint32_t lo = max(o0, s0), hi = min(o1, s2);
         if (lo >= hi) continue;
-        merge_pair_range<EM, P>(Xk, Xv, s0, s1 - s0, s1, s2 - s1, lo - s0, hi - s0, out, s0, lane);
+        merge_pair_range<EM>(X, s0, s1 - s0, s1, s2 - s1, lo - s0, hi - s0, out, s0, lane);
     }
 }
 

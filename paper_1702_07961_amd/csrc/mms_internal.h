@@ -154,10 +154,57 @@ hipError_t launch_merge_pairs(const Phase& ph, const Bufs& b, const RoundArgs& r
 // workgroups walk the phase's tiles.  variant 0: 64x16-key blocks, 8 waves;
 // 1: 64x8-key blocks, 16 waves; 2: 64x8, 8 waves; 3: 64x8, 8 waves, two
 // workgroups per compute unit (registers capped for it; the merge tile must
-// be small enough for two workgroups' LDS).
+// be small enough for two workgroups' LDS); 4: the minBlockHeap merge.
 hipError_t launch_merge_keys(const Phase& ph, const Bufs& b, const RoundArgs& ra, const uint32_t* table,
                              uint32_t flip, unsigned grid, int variant, hipStream_t s);
 
+// Keys-only merge round with a minBlockHeap of 64-key nodes per wave (merge
+// shape 4): one wave per output tile.
+hipError_t launch_merge_heap(const Phase& ph, const Bufs& b, const RoundArgs& ra, const uint32_t* table,
+                             uint32_t flip, hipStream_t s);
+
 hipError_t launch_copy(const uint32_t* in, uint32_t* out, uint64_t n, hipStream_t s);
+
+// ---- 64-bit keys (and 64-bit values): plain sorts only ----------------------
+// Base tiles: kT64Keys keys (8 per lane x 8 waves) or kT64Pairs pairs (8 x
+// 4); merge output tiles kTout64Keys / kTout64Pairs (two workgroups' LDS per
+// compute unit).
+constexpr uint32_t kT64Keys = 4096;
+constexpr uint32_t kT64Pairs = 2048;
+constexpr uint32_t kTout64Keys = 4096;
+constexpr uint32_t kTout64Pairs = 2048;
+
+struct Bufs64 {
+    const uint64_t* in_k;
+    const uint64_t* in_v;
+    uint64_t* out_k;
+    uint64_t* out_v;
+    uint64_t* ws_k;
+    uint64_t* ws_v;
+};
+// one pass of a plain 64-bit sort over [0, n)
+struct Phase64 {
+    uint64_t n;
+    uint32_t dst_out;     // this pass writes the output (else the workspace)
+    uint32_t final_pass;  // last pass: undo the signed-key mapping
+    uint64_t tiles;
+};
+
+// ---- the merge-path baseline (pairwise, per-thread serial merges) ----------
+constexpr int kMergePathThreads = 256;
+constexpr int kMergePathItems = 15;     // outputs per thread (odd: strided LDS reads spread over banks)
+constexpr uint32_t kMergePathTile = (uint32_t)kMergePathThreads * kMergePathItems;
+
+hipError_t launch_mp_blocksort(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t flip_in, uint32_t flip_out,
+                               hipStream_t s);
+hipError_t launch_mp_partition(const uint32_t* src, uint64_t n, uint64_t L, uint32_t* split, hipStream_t s);
+hipError_t launch_mp_merge(const uint32_t* src, uint32_t* dst, uint64_t n, uint64_t L, const uint32_t* split,
+                           uint32_t flip_out, hipStream_t s);
+
+hipError_t launch_tile_sort64(bool pairs, const Phase64& ph, const Bufs64& b, uint64_t flip, hipStream_t s);
+hipError_t launch_corank_tiles64(const Phase64& ph, const Bufs64& b, const RoundArgs& ra, uint32_t* table,
+                                 hipStream_t s);
+hipError_t launch_merge64(bool pairs, const Phase64& ph, const Bufs64& b, const RoundArgs& ra, const uint32_t* table,
+                          uint64_t flip, hipStream_t s);
 
 }  // namespace mms

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mms_corank.h"
 #include "mms_device.h"
 #include "mms_internal.h"
 
@@ -47,22 +48,6 @@ __device__ __forceinline__ uint32_t chunk_word(uint32_t lane, uint32_t c) {
     }
 }
 
-template <int E, bool P>
-__device__ __forceinline__ void wave_merge_tail(Elem<P> (&r)[E], int lane) {
-#pragma unroll
-    for (int dl = kWave / 2; dl >= 1; dl >>= 1) {
-        const bool lo = (lane & dl) == 0;
-#pragma unroll
-        for (int e = 0; e < E; ++e) r[e] = pick(r[e], shfl_xor(r[e], dl), lo);
-    }
-#pragma unroll
-    for (int d = E / 2; d >= 1; d >>= 1) {
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-            if ((e & d) == 0) cex(r[e], r[e | d]);
-    }
-}
-
 template <int E, int W>
 __global__ __launch_bounds__(W * 64) void k_tile_sort_keys(Phase ph, Bufs b, uint32_t flip) {
     constexpr uint32_t CH = 64u * E;
@@ -87,7 +72,7 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort_keys(Phase ph, Bufs b, uin
         const uint32_t j = (uint32_t)wave * CH + (uint32_t)e * 64u + ul;
         r[e] = j < cnt ? Elem<false>{gptr(in_k)[j] ^ flip} : Elem<false>::sentinel();
     }
-    wave_sort_blocked<E, false>(r, lane);
+    wave_sort_blocked<E>(r, lane);
 
     uint32_t buf = 0;
     // keep the minimum (keep = 0) or the maximum (~0) of each key and the
@@ -122,7 +107,7 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort_keys(Phase ph, Bufs b, uin
         exchange(wave ^ (2 * gw - 1), true, (wave & gw) ? ~0u : 0u);
 #pragma unroll
         for (int dw = gw >> 1; dw >= 1; dw >>= 1) exchange(wave ^ dw, false, (wave & dw) ? ~0u : 0u);
-        wave_merge_tail<E, false>(r, lane);
+        wave_merge_tail<E>(r, lane);
     }
 
     // wave w, lane l holds tile positions w*CH + l*E .. + E-1
@@ -181,7 +166,7 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort_pairs(Phase ph, Bufs b, ui
             r[e] = Elem<true>::sentinel();
         }
     }
-    wave_sort_blocked<E, true>(r, lane);
+    wave_sort_blocked<E>(r, lane);
 
     uint32_t buf = 0;
     auto exchange = [&](int pw, bool mirror, bool want_first) {
@@ -223,7 +208,7 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort_pairs(Phase ph, Bufs b, ui
         exchange(wave ^ (2 * gw - 1), true, (wave & gw) == 0);
 #pragma unroll
         for (int dw = gw >> 1; dw >= 1; dw >>= 1) exchange(wave ^ dw, false, (wave & dw) == 0);
-        wave_merge_tail<E, true>(r, lane);
+        wave_merge_tail<E>(r, lane);
     }
 
     // wave w, lane l holds tile positions w*CH + l*E .. + E-1; values by tag
@@ -248,145 +233,6 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort_pairs(Phase ph, Bufs b, ui
             }
         }
     }
-}
-
-// ===========================================================================
-// Partition (§4.1): split indices c_0..c_{K-1} of K sorted runs at rank r.
-//
-// Exact, with O(log L) dependent probe rounds.  At resolution h (a power of
-// two) call block j of run k its elements [j*h, (j+1)*h) and represent a full
-// block by its last element.  The number of run-k full blocks inside the
-// first r merged elements is floor(c_k / h), and the blocks inside form the
-// smallest such representatives overall (the first r elements are closed
-// downwards).  Their total t_h = sum_k floor(c_k/h) lies in
-// [ceil((r - K(h-1))/h), floor(r/h)], an interval narrower than K.
-// Going from resolution 2h to h, run k can only gain half-blocks of the
-// blocks the previous level left undecided; every such candidate is probed
-// once, the candidates are ranked in the wave, and the bounds on t_h turn
-// into bounds [lo_k, hi_k] on floor(c_k/h) whose widths sum to less than K.
-// So at most 3K-2 candidates exist per level (one per lane for K <= 16), and
-// at h = 1 the bounds meet: c_k = lo_k = hi_k.  Ties are ordered by (key,
-// run, position), the stable order.
-// ===========================================================================
-// Inclusive sum over the 16 lanes of each row (DPP row shifts).
-__device__ __forceinline__ uint32_t row16_incl_sum(uint32_t x) {
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);   // row_shr:1
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);   // row_shr:2
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);   // row_shr:4
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);   // row_shr:8
-    return x;
-}
-
-// Inclusive maximum over all 64 lanes: row shifts, then the row broadcasts of
-// lanes 15 and 31 carry it across rows.
-__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
-    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false));   // row_shr:1
-    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false));   // row_shr:2
-    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false));   // row_shr:4
-    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false));   // row_shr:8
-    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false));   // row_bcast:15
-    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false));   // row_bcast:31
-    return x;
-}
-
-// Set bits of mask at positions [off, off + cnt), off < 64, cnt <= 64 - off.
-__device__ __forceinline__ uint32_t bits_in(uint64_t mask, uint32_t off, uint32_t cnt) {
-    const uint64_t x = mask >> off;
-    return cnt ? (uint32_t)__popcll(x << (64u - cnt)) : 0u;
-}
-
-// A wave's LDS scratch for corank_wave.
-struct CorankLds {
-    uint64_t comp[64];   // candidate (key, lane) of every lane, read back as broadcasts
-    uint32_t head[64];   // level tag | run + 1 at the lane where a run's candidates start
-};
-
-// Returns c_k in lane k (k < Kg <= 16); other lanes return 0.  All 64 lanes
-// call with the same arguments; positions inside a run are below 2^32.
-//
-// Each round refines the resolution by 2^s: s = 1 in general, s = 2 when at
-// most 9 runs take part.  With bounds lo_k <= floor(c_k/h) <= hi_k and
-// sum(hi - lo) < K, the sub-blocks of h' = h/2^s that can still be inside
-// are [2^s lo, 2^s hi + 2^s - 2] (sub-block 2^s(hi+1) - 1 being inside would
-// put c_k past block hi), at most (2^(s+1) - 1)K - 2^s in all: 3K - 2 <= 46
-// for K <= 16, 7K - 4 <= 59 for K <= 9, one per lane either way.
-//
-// The candidates of a round sit in lanes run by run (run k's in lanes off_k ..
-// off_k + cnt_k - 1, in block order), so lane order is (run, block) order and
-// the stable order of candidates is (key, lane).  A lane finds its run from
-// the heads the runs write into LDS (prefix maximum over the lanes; tags grow
-// with the round, so stale heads of earlier rounds lose), ranks its candidate
-// against all others read back from LDS as broadcasts, and the runs count
-// their inside candidates from two ballots.  The sum of the lower bounds is
-// kept as a scalar, so the bounds on t_h need no reduction.
-template <int STEP>
-__device__ uint32_t corank_rounds(const uint32_t* __restrict__ keys, uint64_t gb, uint64_t glen, uint64_t L,
-                                  uint32_t Kg, uint32_t r, uint32_t flip, int lane, CorankLds* sh) {
-    const uint32_t nk = (uint32_t)lane < Kg ? (uint32_t)min(L, glen - (uint64_t)lane * L) : 0u;
-    const uint64_t maxlen = Kg > 1 ? L : glen;
-    cgu32* kp = gptr(keys) + gb;
-    sh->head[lane] = 0u;
-    // resolution 2^l with 2^l > every run: lo = hi = 0 bound floor(c_k / 2^l)
-    int l = maxlen ? 64 - __builtin_clzll(maxlen) : 0;
-    uint32_t lo = 0, hi = 0;   // lane k
-    uint32_t slo = 0;          // sum of lo over the runs
-    uint32_t tag = 0;
-    while (l > 0) {
-        const int s = STEP == 1 ? 1 : min(STEP, l);
-        l -= s;
-        tag += 256u;
-        const uint32_t nb = nk >> l;   // full blocks of run k at resolution 2^l
-        const uint32_t jlo = lo << s;
-        const uint32_t jmax = (hi << s) + (1u << s) - 2u;
-        const uint32_t cnt = nb > jlo ? min(jmax, nb - 1u) - jlo + 1u : 0u;
-        const uint32_t incl = row16_incl_sum(cnt);
-        const uint32_t off = incl - cnt;
-        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 15);
-        if (cnt) sh->head[off] = tag | (uint32_t)(lane + 1);
-        lds_wave_sync();
-        const uint32_t kk = (wave_incl_max(sh->head[lane]) & 0xFFu) - 1u;
-        const bool valid = (uint32_t)lane < total;
-        // block index of this lane's candidate = lane + (jlo - off) of its run
-        const uint32_t d = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(kk << 2), (int)(jlo - off));
-        uint64_t comp = ~0ull;
-        if (valid) {
-            const uint32_t pos = (((uint32_t)lane + d + 1u) << l) - 1u;
-            const uint32_t key = kp[(uint64_t)kk * L + pos] ^ flip;
-            comp = ((uint64_t)key << 32) | (uint32_t)lane;
-        }
-        sh->comp[lane] = comp;
-        lds_wave_sync();
-        uint32_t rank = 0;
-        // two trips' reads in flight: at most 64 VGPRs, eight waves per SIMD
-#pragma unroll 2
-        for (uint32_t m = 0; m < total; m += 8) {
-#pragma unroll
-            for (uint32_t e = 0; e < 8; ++e) rank += sh->comp[m + e] < comp ? 1u : 0u;
-        }
-
-        // t_h in [ceil((r - Kg(h-1)) / h), floor(r / h)]; all wave-uniform
-        const uint64_t hm1 = (1ull << l) - 1u;
-        const uint64_t kh = (uint64_t)Kg * hm1;
-        const uint32_t tlo = (uint64_t)r > kh ? (uint32_t)(((uint64_t)r - kh + hm1) >> l) : 0u;
-        const uint32_t thi = r >> l;
-        const uint32_t sj = slo << s;   // sum of jlo
-        const uint32_t dlo = tlo > sj ? tlo - sj : 0u;
-        const uint32_t dhi = thi > sj ? thi - sj : 0u;
-        const uint32_t mlo = dlo < total ? dlo : total;
-        const uint32_t mhi = dhi < total ? dhi : total;
-        const uint64_t blo = __ballot(valid && rank < mlo);
-        const uint64_t bhi = __ballot(valid && rank < mhi);
-        lo = jlo + bits_in(blo, off, cnt);
-        hi = jlo + bits_in(bhi, off, cnt);
-        slo = sj + (uint32_t)__popcll(blo);
-    }
-    return lo;
-}
-
-__device__ uint32_t corank_wave(const uint32_t* __restrict__ keys, uint64_t gb, uint64_t glen, uint64_t L,
-                                uint32_t Kg, uint32_t r, uint32_t flip, int lane, CorankLds* sh) {
-    if (Kg <= 9) return corank_rounds<2>(keys, gb, glen, L, Kg, r, flip, lane, sh);
-    return corank_rounds<1>(keys, gb, glen, L, Kg, r, flip, lane, sh);
 }
 
 // One wave per tile of a merge round: the split at the tile's first output.
@@ -535,12 +381,12 @@ __global__ __launch_bounds__(W * 64) void k_merge_pairs(Phase ph, Bufs b, RoundA
 
     for (uint32_t lvl = 0; (1u << lvl) < Kg; ++lvl) {
         const bool last = (2u << lvl) >= Kg;
+        const LdsKV32 X{Xk, Xv};
         if (last) {
             GlobalSinkLim<P> out{dst_k + obase, dst_v + obase, flip_out, cnt};
-            merge_level<kEM, P>(Xk, Xv, seg0, Kg, lvl, cnt, out, wave, W, lane);
+            merge_level<kEM>(X, seg0, Kg, lvl, cnt, out, wave, W, lane);
         } else {
-            LdsSink<P> out{Yk, Yv};
-            merge_level<kEM, P>(Xk, Xv, seg0, Kg, lvl, cnt, out, wave, W, lane);
+            merge_level<kEM>(X, seg0, Kg, lvl, cnt, LdsKV32{Yk, Yv}, wave, W, lane);
         }
         lds_barrier();
         uint32_t* tmp = Xk; Xk = Yk; Yk = tmp;

@@ -1,0 +1,323 @@
+// gfx950 kernels of the 64-bit multiway mergesort (§6.3 also sorts 8-byte
+// integers): 64-bit keys alone, or stable pairs of 64-bit keys and 64-bit
+// values.  The method is the one of the 32-bit path:
+//
+//   tile_sort64   base case (§4.3): each workgroup sorts a tile in registers
+//                 (a bitonic network per wave, then bitonic merges across
+//                 the waves through LDS)
+//   corank64      partition (§4.1): the exact split of each output tile
+//   merge64       K-way merge of one output tile through LDS (§4.2, §7):
+//                 the pieces are loaded back to back and merged pairwise in
+//                 log2 K levels of conflict-free block merges
+//
+// Pairs carry (key, tag, value) through every network, the tag being the
+// element's position in the array or LDS buffer the pass reads, so every
+// step is stable and no step gathers by a data-dependent LDS address.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "mms_corank.h"
+#include "mms_device.h"
+#include "mms_device64.h"
+#include "mms_internal.h"
+
+namespace mms {
+
+namespace {
+
+// LDS of one exchange buffer of the base case: keys, then (pairs) values and
+// tags, for T elements
+template <bool PAIRS> constexpr uint32_t xbuf_bytes(uint32_t T) { return T * (PAIRS ? 20u : 8u); }
+
+}  // namespace
+
+// ===========================================================================
+// Base case.  Wave w loads positions w*CH + e*64 + lane (coalesced) and sorts
+// them in registers; lane l then holds positions l*E .. l*E+E-1 of its wave's
+// run.  Level lvl merges runs of 2^lvl waves: a mirror stage pairs element
+// (lane, e) of wave w with element (63-lane, E-1-e) of wave w ^ (2^(lvl+1)-1),
+// then wave-distance stages pair equal slots, each through LDS, and the
+// in-wave tail finishes.  In LDS element (lane, e) of wave w sits at slot
+// w*CH + e*64 + lane, so every exchange access is 64 consecutive elements.
+// ===========================================================================
+template <int E, int W, bool PAIRS>
+__global__ __launch_bounds__(W * 64) void k_tile_sort64(Phase64 ph, Bufs64 b, uint64_t flip) {
+    using El = std::conditional_t<PAIRS, E64V, E64>;
+    constexpr uint32_t CH = 64u * E;
+    constexpr uint32_t T = CH * W;
+    extern __shared__ __align__(16) uint64_t smem64[];
+
+    const int lane = threadIdx.x & 63;
+    const uint32_t ul = (uint32_t)lane;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint64_t base = (uint64_t)blockIdx.x * T;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(T, ph.n - base);
+    uint64_t* out_k = (ph.dst_out ? b.out_k : b.ws_k) + base;
+    uint64_t* out_v = PAIRS ? (ph.dst_out ? b.out_v : b.ws_v) + base : nullptr;
+    const uint64_t flip_out = ph.final_pass ? flip : 0ull;
+
+    El r[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t j = (uint32_t)wave * CH + (uint32_t)e * 64u + ul;
+        if (j < cnt) {
+            if constexpr (PAIRS) r[e] = El{gptr64(b.in_k)[base + j] ^ flip, j, gptr64(b.in_v)[base + j]};
+            else r[e] = El{gptr64(b.in_k)[base + j] ^ flip};
+        } else {
+            r[e] = El::sentinel();
+        }
+    }
+    wave_sort_blocked<E>(r, lane);
+
+    uint32_t buf = 0;
+    auto exchange = [&](int pw, bool mirror, bool want_first) {
+        uint8_t* X = reinterpret_cast<uint8_t*>(smem64) + buf * xbuf_bytes<PAIRS>(T);
+        buf ^= 1u;
+        uint64_t* xk = reinterpret_cast<uint64_t*>(X);
+        uint64_t* xv = xk + T;
+        uint32_t* xt = reinterpret_cast<uint32_t*>(xv + T);
+        const uint32_t me = (uint32_t)wave * CH;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t slot = me + (uint32_t)e * 64u + ul;
+            xk[slot] = r[e].k;
+            if constexpr (PAIRS) {
+                xv[slot] = r[e].v;
+                xt[slot] = r[e].t;
+            }
+        }
+        lds_barrier();
+        const uint32_t them = (uint32_t)pw * CH;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t slot = them + (mirror ? (uint32_t)(E - 1 - e) * 64u + (63u - ul) : (uint32_t)e * 64u + ul);
+            El o;
+            if constexpr (PAIRS) o = El{xk[slot], xt[slot], xv[slot]};
+            else o = El{xk[slot]};
+            r[e] = pick(r[e], o, want_first);
+        }
+    };
+#pragma unroll
+    for (int lvl = 0; (1 << lvl) < W; ++lvl) {
+        const int gw = 1 << lvl;
+        exchange(wave ^ (2 * gw - 1), true, (wave & gw) == 0);
+#pragma unroll
+        for (int dw = gw >> 1; dw >= 1; dw >>= 1) exchange(wave ^ dw, false, (wave & dw) == 0);
+        wave_merge_tail<E>(r, lane);
+    }
+
+    // lane l holds tile positions wave*CH + l*E .. + E-1: pairs of 16 bytes
+    const uint32_t p0 = (uint32_t)wave * CH + ul * (uint32_t)E;
+    const bool vec = ((((uintptr_t)out_k) | (uintptr_t)(PAIRS ? out_v : out_k)) & 15u) == 0;
+    typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(1))) u64x2 gu64x2;
+#pragma unroll
+    for (int e = 0; e < E; e += 2) {
+        const uint32_t pos = p0 + (uint32_t)e;
+        if (vec && pos + 2u <= cnt) {
+            *reinterpret_cast<gu64x2*>(gptr64(out_k) + pos) = u64x2{r[e].k ^ flip_out, r[e + 1].k ^ flip_out};
+            if constexpr (PAIRS) *reinterpret_cast<gu64x2*>(gptr64(out_v) + pos) = u64x2{r[e].v, r[e + 1].v};
+        } else {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (pos + (uint32_t)j < cnt) {
+                    gptr64(out_k)[pos + j] = r[e + j].k ^ flip_out;
+                    if constexpr (PAIRS) gptr64(out_v)[pos + j] = r[e + j].v;
+                }
+            }
+        }
+    }
+}
+
+// ===========================================================================
+// Partition (§4.1): one wave per output tile of a merge round, the split at
+// the tile's first output.  The round reads the buffer it does not write.
+// ===========================================================================
+__global__ __launch_bounds__(256) void k_corank_tiles64(Phase64 ph, Bufs64 b, RoundArgs ra,
+                                                        uint32_t* __restrict__ table) {
+    __shared__ CorankLdsT<uint64_t> sh[4];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint64_t t = (uint64_t)blockIdx.x * 4u + (uint64_t)wave;
+    if (t >= ph.tiles) return;
+    const uint64_t* src = ph.dst_out ? b.ws_k : b.out_k;
+    const uint64_t grp = t / ra.tpg;
+    const uint64_t i = t - grp * ra.tpg;
+    const uint64_t span = (uint64_t)ra.K * ra.L;
+    const uint64_t gb = grp * span;
+    const uint64_t glen = min(span, ph.n - gb);
+    const uint32_t Kg = (uint32_t)((glen + ra.L - 1) / ra.L);
+    uint32_t c = 0;
+    if (i > 0) c = corank_wave<uint64_t>(src, gb, glen, ra.L, Kg, (uint32_t)(i * ra.Tout), 0ull, lane, &sh[wave]);
+    if ((uint32_t)lane < ra.K) table[t * ra.K + (uint64_t)lane] = c;
+}
+
+// ===========================================================================
+// K-way merge of one output tile (§4.2, §7): the tile's pieces of its
+// group's runs, bounded by the split indices of its first and last output,
+// are loaded into LDS back to back, merged pairwise level by level (log2 K
+// levels, 64x8-element blocks, every wave an equal share of each level's
+// outputs), and the last level is written to memory.
+// ===========================================================================
+template <int W, bool PAIRS>
+__global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundArgs ra,
+                                                    const uint32_t* __restrict__ table, uint64_t flip) {
+    constexpr int EM = 8;
+    constexpr uint32_t NT = W * 64u;
+    const uint32_t Tout = ra.Tout, K = ra.K;
+    const uint64_t L = ra.L;
+    extern __shared__ __align__(16) uint64_t smem64[];
+    uint64_t* Xk = smem64;
+    uint64_t* Yk = smem64 + Tout;
+    uint64_t* Xv = PAIRS ? smem64 + 2 * Tout : nullptr;
+    uint64_t* Yv = PAIRS ? smem64 + 3 * Tout : nullptr;
+    uint32_t* seg0 = reinterpret_cast<uint32_t*>(smem64 + (PAIRS ? 4u : 2u) * Tout);   // [kMaxFanout + 1]
+    uint32_t* start = seg0 + kMaxFanout + 1;                                            // [kMaxFanout]
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint64_t t = blockIdx.x;
+    const uint64_t* src_k = ph.dst_out ? b.ws_k : b.out_k;
+    const uint64_t* src_v = ph.dst_out ? b.ws_v : b.out_v;
+    uint64_t* dst_k = ph.dst_out ? b.out_k : b.ws_k;
+    uint64_t* dst_v = ph.dst_out ? b.out_v : b.ws_v;
+    const uint64_t flip_out = ph.final_pass ? flip : 0ull;
+    const uint64_t grp = t / ra.tpg;
+    const uint64_t i = t - grp * ra.tpg;
+    const uint64_t span = (uint64_t)K * L;
+    const uint64_t gb = grp * span;
+    const uint64_t glen = min(span, ph.n - gb);
+    const uint32_t Kg = (uint32_t)((glen + L - 1) / L);
+    const uint64_t obeg = i * (uint64_t)Tout;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(Tout, glen - obeg);
+    const uint64_t obase = gb + obeg;
+
+    if (Kg == 1) {   // a lone run: its tile is already in order
+        for (uint32_t j = threadIdx.x; j < cnt; j += NT) {
+            gptr64(dst_k)[obase + j] = gptr64(src_k)[obase + j] ^ flip_out;
+            if constexpr (PAIRS) gptr64(dst_v)[obase + j] = gptr64(src_v)[obase + j];
+        }
+        return;
+    }
+    if (wave == 0) {   // lane k < Kg: piece k; piece starts by a row prefix sum
+        uint32_t len = 0;
+        if ((uint32_t)lane < Kg) {
+            const uint32_t k = (uint32_t)lane;
+            const uint64_t nk = min(L, glen - (uint64_t)k * L);
+            // the clamps only guard memory safety; exact splits never trigger them
+            const uint32_t s = i == 0 ? 0u : min(table[t * K + k], (uint32_t)nk);
+            const uint32_t e = (obeg + Tout >= glen) ? (uint32_t)nk : min(table[(t + 1) * K + k], (uint32_t)nk);
+            start[k] = s;
+            len = e > s ? e - s : 0u;
+        }
+        const uint32_t incl = row16_incl_sum(len);
+        if ((uint32_t)lane < Kg) seg0[lane + 1] = min(incl, cnt);
+        if (lane == 0) seg0[0] = 0;
+    }
+    lds_barrier();
+    {
+        // every thread issues the loads of all its slots at once (slot j lies
+        // in the last piece k with seg0[k] <= j), then parks them in LDS
+        constexpr int PER = (int)((kTout64Keys + NT - 1u) / NT);
+        const uint32_t filled = seg0[Kg];
+        uint64_t lk[PER], lv[PER];
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const uint32_t j = (uint32_t)r * NT + threadIdx.x;
+            lk[r] = 0;
+            lv[r] = 0;
+            if (j < filled) {
+                uint32_t lo = 0, hi = Kg;
+                while (hi - lo > 1u) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (seg0[mid] <= j) lo = mid;
+                    else hi = mid;
+                }
+                const uint64_t sp = gb + (uint64_t)lo * L + start[lo] + (j - seg0[lo]);
+                lk[r] = gptr64(src_k)[sp];
+                if constexpr (PAIRS) lv[r] = gptr64(src_v)[sp];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const uint32_t j = (uint32_t)r * NT + threadIdx.x;
+            if (j < filled) {
+                Xk[j] = lk[r];
+                if constexpr (PAIRS) Xv[j] = lv[r];
+            }
+        }
+    }
+    lds_barrier();
+
+    for (uint32_t lvl = 0; (1u << lvl) < Kg; ++lvl) {
+        const bool last = (2u << lvl) >= Kg;
+        if constexpr (PAIRS) {
+            const LdsKV64 X{Xk, Xv};
+            if (last) merge_level<EM>(X, seg0, Kg, lvl, cnt, GlobalSinkKV64{dst_k + obase, dst_v + obase, flip_out, cnt},
+                                      wave, W, lane);
+            else merge_level<EM>(X, seg0, Kg, lvl, cnt, LdsKV64{Yk, Yv}, wave, W, lane);
+        } else {
+            const LdsK64 X{Xk};
+            if (last) merge_level<EM>(X, seg0, Kg, lvl, cnt, GlobalSinkK64{dst_k + obase, flip_out, cnt}, wave, W, lane);
+            else merge_level<EM>(X, seg0, Kg, lvl, cnt, LdsK64{Yk}, wave, W, lane);
+        }
+        lds_barrier();
+        uint64_t* tmp = Xk; Xk = Yk; Yk = tmp;
+        tmp = Xv; Xv = Yv; Yv = tmp;
+    }
+}
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+static hipError_t allow_lds64(const void* f, size_t bytes) {
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_tile_sort64(bool pairs, const Phase64& ph, const Bufs64& b, uint64_t flip, hipStream_t s) {
+    if (ph.tiles == 0) return hipSuccess;
+    if (pairs) {
+        constexpr int E = 8, W = 4;
+        static_assert(64u * E * W == kT64Pairs, "pairs base tile");
+        const size_t lds = 2u * xbuf_bytes<true>(kT64Pairs);
+        hipError_t e = allow_lds64((const void*)k_tile_sort64<E, W, true>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_tile_sort64<E, W, true>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, flip);
+    } else {
+        constexpr int E = 8, W = 8;
+        static_assert(64u * E * W == kT64Keys, "keys base tile");
+        const size_t lds = 2u * xbuf_bytes<false>(kT64Keys);
+        hipError_t e = allow_lds64((const void*)k_tile_sort64<E, W, false>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_tile_sort64<E, W, false>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, flip);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_corank_tiles64(const Phase64& ph, const Bufs64& b, const RoundArgs& ra, uint32_t* table,
+                                 hipStream_t s) {
+    if (ph.tiles == 0) return hipSuccess;
+    const uint64_t blocks = (ph.tiles + 3) / 4;
+    hipLaunchKernelGGL(k_corank_tiles64, dim3((unsigned)blocks), dim3(256), 0, s, ph, b, ra, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge64(bool pairs, const Phase64& ph, const Bufs64& b, const RoundArgs& ra, const uint32_t* table,
+                          uint64_t flip, hipStream_t s) {
+    if (ph.tiles == 0) return hipSuccess;
+    if (ra.K > kMaxFanout || ra.Tout > (pairs ? kTout64Pairs : kTout64Keys)) return hipErrorInvalidValue;
+    constexpr int W = 8;
+    const size_t lds = (pairs ? 4u : 2u) * ra.Tout * sizeof(uint64_t) + (2u * kMaxFanout + 4u) * sizeof(uint32_t);
+    const void* f = pairs ? (const void*)k_merge64<W, true> : (const void*)k_merge64<W, false>;
+    hipError_t e = allow_lds64(f, lds);
+    if (e != hipSuccess) return e;
+    if (pairs)
+        hipLaunchKernelGGL((k_merge64<W, true>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, ra, table, flip);
+    else
+        hipLaunchKernelGGL((k_merge64<W, false>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, ra, table, flip);
+    return hipGetLastError();
+}
+
+}  // namespace mms

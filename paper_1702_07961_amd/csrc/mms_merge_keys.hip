@@ -435,6 +435,7 @@ hipError_t launch_merge_keys(const Phase& ph, const Bufs& b, const RoundArgs& ra
                              uint32_t flip, unsigned grid, int variant, hipStream_t s) {
     if (ra.Tout > kToutKeys || ra.K > kMaxFanout || ra.Tout % 4 || ra.L % 4) return hipErrorInvalidValue;
     if (ph.tiles == 0) return hipSuccess;
+    if (variant == 4) return launch_merge_heap(ph, b, ra, table, flip, s);
     if (variant == 1) return launch_variant<8, 16, 1>(ph, b, ra, table, flip, grid, s);
     if (variant == 2) return launch_variant<8, 8, 1>(ph, b, ra, table, flip, grid, s);
     if (variant == 3) return launch_variant<8, 8, 4>(ph, b, ra, table, flip, grid, s);

@@ -1,5 +1,6 @@
 """Input generators: determinism, published constants and closed forms."""
 import numpy as np
+import pytest
 
 import mmsgen
 
@@ -65,3 +66,31 @@ def test_poisson_arrivals_rate():
     t = mmsgen.poisson_arrivals(13, 20000, rate=1000.0)
     assert np.all(np.diff(t) > 0)
     assert abs(t[-1] / 20.0 - 1) < 0.05
+
+
+def test_mergepath_adversary_is_a_permutation_with_its_pattern():
+    """Every merge of two runs of h keys (runs at every level, h >= 15) takes,
+    in the first half of its 15-output thread windows, 15, 15 and 2 outputs
+    of every three from its first run, and mirrors that in the second half."""
+    vt = 15
+    n = vt * 2**9
+    x = mmsgen.mergepath_adversary_u32(n)
+    assert np.array_equal(np.sort(x), np.arange(n, dtype=np.uint32))
+    length = n
+    while length > vt:
+        h = length // 2
+        for s in range(0, n, length):
+            a = set(x[s:s + h].tolist())
+            merged = np.sort(x[s:s + length])
+            from_a = np.array([v in a for v in merged.tolist()])
+            per_thread = from_a.reshape(-1, vt).sum(1)
+            t = per_thread.size
+            head = per_thread[: max(0, t // 2 - 3)]
+            want = np.tile([15, 15, 2], head.size // 3 + 1)[: head.size]
+            assert np.array_equal(head, want), (length, s)
+            assert from_a.sum() == h
+        length = h
+    # runs of vt keys descend
+    assert np.all(np.diff(x[:vt].astype(np.int64)) < 0)
+    with pytest.raises(ValueError):
+        mmsgen.mergepath_adversary_u32(vt * 3)

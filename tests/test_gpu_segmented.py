@@ -156,3 +156,40 @@ def test_segmented_base_tiles(mms, base):
     finally:
         mms.set_tuning([])
         mms._lib.load_tuning(mms._lib.lib())
+
+
+def test_segmented_workspace_reused_between_replays(mms):
+    """The batch metadata lives in the caller's workspace and is copied in
+    on every call: clobbering the whole workspace between graph replays must
+    not change the results."""
+    sizes = mmsgen.loguniform_sizes(mmsgen.seed_for(4, 20), 200, 8, 17).astype(np.int64)
+    off = offsets_of(sizes)
+    n = int(off[-1])
+    ws = torch.empty(mms.segmented_workspace_bytes(off), dtype=torch.uint8, device="cuda")
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    for trial in range(4):
+        x = mmsgen.uniform_u32(mmsgen.seed_for(4, 21 + trial), n)
+        ws.fill_(0xA5 + trial)
+        mms.segmented_sort(dev(x), off, out_keys=out, workspace=ws, i32=False)
+        assert np.array_equal(host(out), oracle.sort_segments(x, off)), trial
+
+
+def test_segmented_signature_cache_eviction(mms):
+    """More distinct offset signatures than the library caches (8), enqueued
+    back to back on one stream with no synchronisation in between: evicting
+    an entry must wait for its launches, and every result must be exact."""
+    cases = []
+    for i in range(11):
+        sizes = [300 + 97 * i, 0, 2048 * (i + 1) + 5, 40_000 + 1000 * i]
+        off = offsets_of(sizes)
+        x = mmsgen.uniform_u32(mmsgen.seed_for(4, 40 + i), int(off[-1]))
+        xd = dev(x)
+        out = torch.empty_like(xd)
+        ws = torch.empty(mms.segmented_workspace_bytes(off), dtype=torch.uint8, device="cuda")
+        cases.append((x, off, xd, out, ws))
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for x, off, xd, out, ws in cases:
+            mms.segmented_sort(xd, off, out_keys=out, workspace=ws, i32=False)
+    for x, off, xd, out, ws in cases:
+        assert np.array_equal(host(out), oracle.sort_segments(x, off))

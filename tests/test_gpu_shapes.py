@@ -1,0 +1,106 @@
+"""GPU parity of every keys-only merge shape the library ships, against the
+oracle, element by element.
+
+The keys merge has five kernel shapes (variant 0: 64x16-key blocks with 8
+waves, the built-in default; 1: 64x8-key blocks with 16 waves; 2: 64x8 with
+8 waves; 3: as 2 with two workgroups per compute unit; 4: the minBlockHeap
+merge, one heap of 64-key nodes per wave).  Each is run under
+every fan-out K in {2, 4, 8, 16} and merge tiles of 2048, 6144 and 8192 keys,
+on unsigned and signed keys, at a size where every workgroup of the
+persistent grid walks several tiles per round (so the pipeline's prefetch,
+its four-table ring and the buffer swap all run) and the last merge group is
+ragged.  The oracle sorts each input once; every shape must reproduce it.
+"""
+import numpy as np
+import pytest
+
+import mmsgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# 2^23 + 12345 keys: with 8192-key merge tiles a round has 1026 tiles, at
+# least 4 per workgroup of any shape's persistent grid (at most 256 compute
+# units x 4 workgroups for the smallest LDS footprint at 2048-key tiles,
+# which has 4102 tiles); the last group of every round is partial.
+N_SWEEP = (1 << 23) + 12345
+VARIANTS = [0, 1, 2, 3, 4]
+FANOUTS = [2, 4, 8, 16]
+TOUTS = [2048, 6144, 8192]
+# base-case shape per variant (2048-, 4096- and 8192-key tiles all appear)
+BASE_OF_VARIANT = {0: 0, 1: 4, 2: 3, 3: 6, 4: 3}
+
+
+@pytest.fixture(scope="module")
+def mms():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1702_07961_amd as m
+    m._lib.lib()
+    yield m
+    m.set_tuning([])
+    m._lib.load_tuning(m._lib.lib())
+
+
+@pytest.fixture(scope="module")
+def sweep_input():
+    x = mmsgen.uniform_u32(mmsgen.seed_for(13, 0), N_SWEEP)
+    # a tenth of the keys from a 64-value range: long runs of ties cross tiles
+    u = mmsgen.unit_doubles(mmsgen.seed_for(13, 1), N_SWEEP)
+    few = (mmsgen.uniform_u32(mmsgen.seed_for(13, 2), N_SWEEP) % np.uint32(64)) * np.uint32(0x04000001)
+    x = np.where(u < 0.1, few, x).astype(np.uint32)
+    return x, oracle.sort(x), oracle.sort(x, i32=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_merge_shape_sweep(mms, sweep_input, variant):
+    x, want_u, want_s = sweep_input
+    xd = dev(x)
+    out = torch.empty_like(xd)
+    base = BASE_OF_VARIANT[variant]
+    for K in FANOUTS:
+        for tout in TOUTS:
+            mms.set_tuning([(64, K, tout, variant, base)])
+            assert mms.get_tuning(N_SWEEP)[1:4] == (K, tout, variant)
+            p = mms.plan(N_SWEEP)
+            assert p.rounds >= 2
+            mms.sort(xd, out=out, i32=False)
+            assert np.array_equal(host(out), want_u), (variant, K, tout, "u32")
+            mms.sort(xd, out=out, i32=True)
+            assert np.array_equal(host(out), want_s), (variant, K, tout, "i32")
+
+
+def test_builtin_default_through_c_abi(mms, sweep_input):
+    """With no tuning table the C ABI uses its built-in default (K = 16,
+    8192-key merge tiles, merge shape 0, base shape 0): the entry point a C
+    caller gets without mms_set_tuning."""
+    x, want_u, want_s = sweep_input
+    mms.set_tuning([])
+    t = mms.get_tuning(N_SWEEP)
+    assert t[1:5] == (16, 8192, 0, 0)
+    xd = dev(x)
+    assert np.array_equal(host(mms.sort(xd, i32=False)), want_u)
+    assert np.array_equal(host(mms.sort(xd, i32=True)), want_s)
+    for n in [1, 2047, 2049, 16 * 2048 + 1, 300_001, 3_000_017]:
+        y = x[:n].copy()
+        assert np.array_equal(host(mms.sort(dev(y), i32=False)), oracle.sort(y)), n
+
+
+def test_loaded_table_between_buckets(mms):
+    """Plain sorts under the shipped table at sizes whose buckets pick the
+    16-wave merge shape (2^21) and the two-workgroup shape (2^22 and up)."""
+    mms.set_tuning([])
+    mms._lib.load_tuning(mms._lib.lib())
+    for n in [1_500_007, (1 << 21) - 3, (1 << 22) + 1001]:
+        x = mmsgen.uniform_u32(mmsgen.seed_for(13, 3 + n % 5), n)
+        assert np.array_equal(host(mms.sort(dev(x), i32=False)), oracle.sort(x)), n
