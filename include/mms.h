@@ -139,6 +139,24 @@ int mms_sort_mergepath_u32(const uint32_t* d_in, uint32_t* d_out, uint64_t n,
                            void* d_ws, size_t ws_bytes, uint32_t flags, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid allocation): mms_sort_u32 without a
+ * workspace argument.  The workspace is a fixed array of
+ * MMS_NOALLOC_SCRATCH_BYTES bytes of device memory inside the library, one
+ * copy on each GPU it runs on, held until the process ends; the call itself
+ * allocates nothing (its first call on a device looks up that device's copy).
+ * Sorts n keys ascending exactly as mms_sort_u32 does (uint32, or int32 with
+ * MMS_KEY_I32), on `stream`, with the same buffer rules.  Every call on one
+ * GPU shares that GPU's array, so calls whose work may overlap on one GPU
+ * (other streams, other threads) race; serialise them.  Errors: MMS_EINVAL
+ * (flags, pointers, overlap, n >= 2^32, or n whose workspace,
+ * mms_workspace_bytes(n, flags), exceeds MMS_NOALLOC_SCRATCH_BYTES: about
+ * 1.6e7 keys), MMS_EHIP (launch failure).
+ */
+#define MMS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int mms_sort_u32_noalloc(const uint32_t* d_in, uint32_t* d_out, uint64_t n, uint32_t flags, void* stream);
+
+/*
  * §4.1 parallel partitioning on its own: split indices of groups of K sorted
  * runs at given ranks.  The n elements of d_keys form groups of K runs laid
  * out back to back: run k of group g starts at g*K*run_len + k*run_len and

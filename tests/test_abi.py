@@ -113,6 +113,19 @@ def test_sort_argument_errors(lib):
     assert lib.mms_sort_u32(FAKE, FAKE, 0, None, 0, 0, None) == _lib.MMS_OK
 
 
+def test_noalloc_argument_errors(lib):
+    """Rejections of the no-workspace sort happen before any device call."""
+    limit = 64 << 20
+    big = 1
+    while lib.mms_workspace_bytes(big, 0) <= limit:
+        big *= 2
+    assert lib.mms_sort_u32_noalloc(FAKE, FAKE + 2**34, big, 0, None) == _lib.MMS_EINVAL
+    assert b"scratch" in lib.mms_last_error()
+    assert lib.mms_sort_u32_noalloc(FAKE, FAKE + 2**34, 1 << 32, 0, None) == _lib.MMS_EINVAL
+    assert lib.mms_sort_u32_noalloc(FAKE, FAKE + 2**34, 1000, _lib.MMS_PAIRS, None) == _lib.MMS_EINVAL
+    assert lib.mms_sort_u32_noalloc(FAKE, FAKE, 0, 0, None) == _lib.MMS_OK
+
+
 def test_pairs_argument_errors(lib):
     n = 100_000
     ws = lib.mms_workspace_bytes(n, _lib.MMS_PAIRS)
