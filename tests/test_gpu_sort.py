@@ -199,7 +199,8 @@ def test_partition_against_oracle(mms, Kq, L, n, tie):
 
 
 def test_copy(mms):
-    for n in [1, 3, 4, 1000, 1 << 20, (1 << 20) + 3]:
+    # up to several grid-stride trips per workgroup (16384 x 256 lanes x 8 chunks of 4 keys per trip)
+    for n in [1, 3, 4, 1000, 1 << 20, (1 << 20) + 3, (3 << 27) + 5]:
         x = mmsgen.uniform_u32(n, n)
         out = torch.empty(n, dtype=torch.int32, device="cuda")
         mms.copy(dev(x), out)
