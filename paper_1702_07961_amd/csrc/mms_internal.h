@@ -103,18 +103,24 @@ __device__ __forceinline__ TileRef tile_ref(const Phase& ph, const Bufs& b, uint
         r.final_pass = ph.final_pass != 0;
         return r;
     }
-    const TileTask tk = ph.tasks[t];
-    const SegDesc& sd = ph.segs[tk.seg];
-    dst_out = (tk.info & kTaskDstOut) != 0;
-    r.in_k = sd.in_k;
-    r.in_v = sd.in_v;
-    r.src_k = dst_out ? sd.ws_k : sd.out_k;
-    r.src_v = dst_out ? sd.ws_v : sd.out_v;
-    r.dst_k = dst_out ? sd.out_k : sd.ws_k;
-    r.dst_v = dst_out ? sd.out_v : sd.ws_v;
-    r.n = sd.n;
-    r.local = tk.info & kTaskTileMask;
-    r.final_pass = (tk.info & kTaskFinal) != 0;
+    // the task list and the descriptors are uniform and read-only during a
+    // launch: scalar loads, which a wave's waits for its vector loads do not
+    // hold up
+    typedef const __attribute__((address_space(4))) TileTask ScalarTask;
+    typedef const __attribute__((address_space(4))) SegDesc ScalarSeg;
+    ScalarTask* tk = (ScalarTask*)ph.tasks + t;
+    const uint32_t info = tk->info;
+    ScalarSeg* sd = (ScalarSeg*)ph.segs + tk->seg;
+    dst_out = (info & kTaskDstOut) != 0;
+    r.in_k = sd->in_k;
+    r.in_v = sd->in_v;
+    r.src_k = dst_out ? sd->ws_k : sd->out_k;
+    r.src_v = dst_out ? sd->ws_v : sd->out_v;
+    r.dst_k = dst_out ? sd->out_k : sd->ws_k;
+    r.dst_v = dst_out ? sd->out_v : sd->ws_v;
+    r.n = sd->n;
+    r.local = info & kTaskTileMask;
+    r.final_pass = (info & kTaskFinal) != 0;
     return r;
 }
 

@@ -92,6 +92,41 @@ __device__ __forceinline__ void load_split(const uint32_t* __restrict__ table, u
     }
 }
 
+// Split indices of a tile for run `lane` (lanes < Kg) from its two table
+// rows held in LDS (row t at rows[0..K), row t+1 at rows[K..2K)), with the
+// same guards as load_split.
+__device__ __forceinline__ void split_from_rows(const uint32_t* rows, const TileGeo& g, uint64_t L, uint32_t K,
+                                                int lane, uint32_t& s, uint32_t& e) {
+    s = 0;
+    e = 0;
+    if ((uint32_t)lane < g.Kg) {
+        const uint32_t k = (uint32_t)lane;
+        const uint32_t nk = (uint32_t)min(L, g.glen - (uint64_t)k * L);
+        const uint32_t sk = g.first ? 0u : min(rows[k], nk);
+        s = sk;
+        e = g.last ? nk : min(max(rows[K + k], sk), nk);
+    }
+}
+
+// Wait until every vector memory operation the wave has issued is complete.
+__device__ __forceinline__ void vm_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Rows t and t+1 of the split table (2K consecutive words; the table has a
+// row past the last tile) copied into LDS by the memory unit, one word per
+// lane, without passing through registers.  The copy is complete once the
+// wave's vector memory counter has drained past it.
+__device__ __forceinline__ void fetch_rows_async(const uint32_t* __restrict__ table, uint64_t t, uint32_t K,
+                                                 uint32_t* rows, int lane) {
+    // the rows' address as a wave-uniform base plus a per-lane offset
+    const uint64_t base = (uint64_t)(uintptr_t)(table + t * K);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(base >> 32));
+    const uint32_t* row = (const uint32_t*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+    if ((uint32_t)lane < 2u * K)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(row + (uint32_t)lane),
+                                         (__attribute__((address_space(3))) void*)rows, 4, 0, 0);
+}
+
 // Piece table of a tile, written by wave 0: start[k] (inside run k),
 // plen[k] (prefix of piece lengths), sbeg[k] (4-aligned LDS offsets).
 struct Meta {
@@ -250,44 +285,60 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
     const int lL = __builtin_ctzll(L);
 
     // registers of the prefetch stage: chunks of 4 LDS slots per thread
-    uint4 pf_val[PC];
+    u32x4a4 pf_val[PC];
     uint32_t pf_dst[PC];
-    uint32_t nx_s = 0, nx_e = 0;   // wave 0: split indices of tile t+3G (at loop start)
+    // wave 0: split-table rows of tile t+3G (at loop start), copied in by the
+    // memory unit one tile ahead
+    uint32_t* rows = mbase + 4u * kMetaWords;
 
     // Chunk P (a multiple of 4 in LDS slot coordinates) lies in piece k with
     // sbeg[k] <= P < sbeg[k] + len_k rounded up to 4, so off = P - sbeg[k] <
-    // len_k: its first key exists; it is read with one 16-byte load when all
-    // four do (global addresses are only 4-byte aligned), else key by key.
-    // Slots past a piece's end are padding that no merge step reads.
+    // len_k: its first key exists.  Every chunk is one 16-byte load (global
+    // addresses are only 4-byte aligned) of the four keys from its first one
+    // on; keys past the piece's end land in padding slots that no merge step
+    // reads.  A chunk that would read past the group's last key is read d
+    // keys earlier instead and shifted back by d as it is stored (groups of
+    // two or more runs hold more than one base tile; a lone run is not loaded
+    // at all, its tile is copied from memory).  One load form for every chunk
+    // keeps all of a thread's loads in flight together.
     auto issue_loads = [&](const TileGeo& g, const Meta& m) {
+        if (g.Kg < 2) {
+#pragma unroll
+            for (int r = 0; r < PC; ++r) pf_dst[r] = 0xFFFFFFFFu;
+            return;
+        }
         const uint32_t slots = m.sbeg[g.Kg];
+        const uint32_t glen = (uint32_t)g.glen;
+        cgu32* gsrc = gptr(g.src) + g.gb;
 #pragma unroll
         for (int r = 0; r < PC; ++r) {
-            const uint32_t P = 4u * ((uint32_t)r * NT + tid);
-            pf_dst[r] = 0xFFFFFFFFu;
-            if (P < slots) {
-                uint32_t k = m.cseg[P >> 6];
-                while (k + 1u < g.Kg && m.sbeg[k + 1u] <= P) ++k;
-                const uint32_t off = P - m.sbeg[k];
-                const uint32_t len = m.plen[k + 1u] - m.plen[k];
-                cgu32* sp = gptr(g.src) + g.gb + (uint64_t)k * L + m.start[k] + off;
-                if (off + 4u <= len) {
-                    const u32x4a4 v = *reinterpret_cast<cgu32x4a4*>(sp);
-                    pf_val[r] = make_uint4(v.x, v.y, v.z, v.w);
-                } else {
-                    pf_val[r].x = sp[0];
-                    pf_val[r].y = off + 1u < len ? sp[1] : 0u;
-                    pf_val[r].z = off + 2u < len ? sp[2] : 0u;
-                    pf_val[r].w = 0u;
-                }
-                pf_dst[r] = P;
-            }
+            // every lane loads (a lane past the tile's last chunk reads chunk
+            // 0 again and discards it), so no load sits under a branch
+            const uint32_t P0 = 4u * ((uint32_t)r * NT + tid);
+            const bool used = P0 < slots;
+            const uint32_t P = used ? P0 : 0u;
+            uint32_t k = m.cseg[P >> 6];
+            while (k + 1u < g.Kg && m.sbeg[k + 1u] <= P) ++k;
+            const uint32_t q = k * (uint32_t)L + m.start[k] + (P - m.sbeg[k]);   // inside the group
+            const uint32_t d = q + 4u > glen ? q + 4u - glen : 0u;                 // 0..3
+            pf_val[r] = *reinterpret_cast<cgu32x4a4*>(gsrc + (q - d));
+            pf_dst[r] = used ? (P | (d << 30)) : 0xFFFFFFFFu;
         }
     };
     auto store_loads = [&](uint32_t* X) {
 #pragma unroll
-        for (int r = 0; r < PC; ++r)
-            if (pf_dst[r] != 0xFFFFFFFFu) *reinterpret_cast<uint4*>(X + pf_dst[r]) = pf_val[r];
+        for (int r = 0; r < PC; ++r) {
+            if (pf_dst[r] != 0xFFFFFFFFu) {
+                u32x4a4 v = pf_val[r];
+                const uint32_t d = pf_dst[r] >> 30;
+                if (d) {   // key j of the chunk is component j + d
+                    v.x = d == 1u ? v.y : d == 2u ? v.z : v.w;
+                    v.y = d == 1u ? v.z : v.w;
+                    v.z = v.w;
+                }
+                *reinterpret_cast<u32x4*>(X + (pf_dst[r] & 0x3FFFFFFFu)) = v;
+            }
+        }
     };
 
     // Pipeline: while tile t is merged, the keys of tile t+G are in flight
@@ -297,28 +348,30 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
     // every step reads what an earlier tile's barriers published.
     // Prologue: whole piece tables of the first two tiles, the layout of the
     // third, the split indices of the fourth, and the first tile's keys.
+    // Tile geometries are recomputed where they are used (a few scalar
+    // instructions each) rather than carried across iterations.
     auto nxt = [](int i) { return (i + 1) & 3; };
-    TileGeo g = tile_geo(ph, b, t, ra, lL);
-    TileGeo g1 = tile_geo(ph, b, t + G < tiles ? t + G : t, ra, lL);
     {
+        const TileGeo g = tile_geo(ph, b, t, ra, lL);
         if (wave == 0) {
             uint32_t s, e;
             load_split(table, t, g, L, K, lane, s, e);
             build_meta<W>(meta(0), s, e, g, lane);
             if (t + G < tiles) {
+                const TileGeo g1 = tile_geo(ph, b, t + G, ra, lL);
                 load_split(table, t + G, g1, L, K, lane, s, e);
                 build_meta<W>(meta(1), s, e, g1, lane);
                 if (t + 2 * G < tiles) {
                     const TileGeo gp = tile_geo(ph, b, t + 2 * G, ra, lL);
                     load_split(table, t + 2 * G, gp, L, K, lane, s, e);
                     build_pieces(meta(2), s, e, gp, lane);
-                    if (t + 3 * G < tiles)
-                        load_split(table, t + 3 * G, tile_geo(ph, b, t + 3 * G, ra, lL), L, K, lane, nx_s, nx_e);
+                    if (t + 3 * G < tiles) fetch_rows_async(table, t + 3 * G, K, rows, lane);
                 }
             }
         }
         lds_barrier();
         issue_loads(g, meta(0));
+        if (wave == 0) vm_drain();   // the rows copy is older than these loads
         store_loads(bufA);
         lds_barrier();
     }
@@ -327,6 +380,7 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
     uint32_t* in = bufA;      // LDS buffer holding the current tile's pieces
     uint32_t* other = bufB;
     for (;;) {
+        const TileGeo g = tile_geo(ph, b, t, ra, lL);
         uint32_t* dst = g.dst;
         const uint32_t flip_out = g.final_pass ? flip : 0u;
         const Meta mc = meta(cur);
@@ -334,27 +388,30 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
         const uint64_t tn = t + G, t2 = t + 2 * G;
         const bool has_next = tn < tiles, has2 = t2 < tiles;
 
+        // wave 0: piece layout of tile t+3G from its split-table rows (copied
+        // into LDS one tile ago), then the copy of tile t+4G's rows; it is
+        // complete once wave 0 drains its memory counter before storing the
+        // next tile's keys below
+        const uint64_t t3 = t2 + G;
+        if (wave == 0 && has2 && t3 < tiles) {
+            const TileGeo g3 = tile_geo(ph, b, t3, ra, lL);
+            uint32_t s3, e3;
+            split_from_rows(rows, g3, L, K, lane, s3, e3);
+            build_pieces(meta(nxt(nxt(nxt(cur)))), s3, e3, g3, lane);
+            if (t3 + G < tiles) fetch_rows_async(table, t3 + G, K, rows, lane);
+        }
+        // waves 1 and 2: chunk table and wave plan of tile t+2G
+        if (has2 && (wave == 1 || wave == 2)) {
+            const Meta m2 = meta(nxt(nxt(cur)));
+            const uint32_t kg2 = tile_geo(ph, b, t2, ra, lL).Kg;
+            if (wave == 1) build_chunks(m2, kg2, lane);
+            else build_plan<W>(m2, kg2, lane);
+        }
         // the next tile's keys go in flight now and land during the last level
         bool issued = false, stored = false;
         if (has_next) {
-            issue_loads(g1, mn);
+            issue_loads(tile_geo(ph, b, tn, ra, lL), mn);
             issued = true;
-        }
-        // geometry of tile t+2G (of tile t when there is none: no select
-        // between structs is needed)
-        const TileGeo g2 = tile_geo(ph, b, has2 ? t2 : t, ra, lL);
-        // waves 1 and 2: chunk table and wave plan of tile t+2G; wave 0:
-        // piece layout of tile t+3G, split indices of tile t+4G
-        if (has2) {
-            const Meta m2 = meta(nxt(nxt(cur)));
-            if (wave == 1) build_chunks(m2, g2.Kg, lane);
-            if (wave == 2) build_plan<W>(m2, g2.Kg, lane);
-            const uint64_t t3 = t2 + G;
-            if (wave == 0 && t3 < tiles) {
-                build_pieces(meta(nxt(nxt(nxt(cur)))), nx_s, nx_e, tile_geo(ph, b, t3, ra, lL), lane);
-                if (t3 + G < tiles)
-                    load_split(table, t3 + G, tile_geo(ph, b, t3 + G, ra, lL), L, K, lane, nx_s, nx_e);
-            }
         }
 
         uint32_t* X = in;
@@ -362,8 +419,8 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
         const uint64_t obase = g.gb + g.obeg;
         uint32_t nlev = 0;
         while ((1u << nlev) < g.Kg) ++nlev;
-        if (g.Kg == 1) {
-            for (uint32_t j = tid; j < g.cnt; j += NT) gptr(dst)[obase + j] = X[j] ^ flip_out;
+        if (g.Kg == 1) {   // a lone run: its tile is already in order
+            for (uint32_t j = tid; j < g.cnt; j += NT) gptr(dst)[obase + j] = gptr(g.src)[obase + j] ^ flip_out;
         } else {
             const bool vec = ((uintptr_t)(dst + obase) & 15u) == 0;
             for (uint32_t lvl = 0; lvl < nlev; ++lvl) {
@@ -373,6 +430,7 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
                 // tile's keys go there, and the barrier after the last level
                 // publishes them
                 if (last && lvl > 0 && issued) {
+                    if (wave == 0) vm_drain();
                     store_loads(Y);
                     stored = true;
                 }
@@ -395,27 +453,33 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
             other = Y;
         } else {
             lds_barrier();        // every wave is done reading this tile's LDS
+            if (wave == 0) vm_drain();
             store_loads(in);
             lds_barrier();
         }
         t = tn;
-        g = g1;
-        g1 = g2;
         cur = nxt(cur);
     }
 }
+
+// Largest merge tile for which two 8-wave workgroups of 64x8-key blocks fit
+// in one compute unit's 160 KiB of LDS.
+constexpr uint32_t kTout2PerCU = 7168;
 
 static hipError_t allow_lds(const void* f, size_t bytes) {
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int EM, int W, int MINW>
+// TMAX: the largest merge tile the shape accepts (it sizes the prefetch
+// registers: chunks of 4 slots per thread for TMAX keys plus up to 3 padding
+// slots per piece).
+template <int EM, int W, int MINW, uint32_t TMAX>
 static hipError_t launch_variant(const Phase& ph, const Bufs& b, const RoundArgs& ra, const uint32_t* table,
                                  uint32_t flip, unsigned grid, hipStream_t s) {
-    // chunks of 4 slots per thread: a tile holds at most kToutKeys keys plus
-    // up to 3 padding slots per piece
-    constexpr int PC = (int)((kToutKeys + 4u * kMaxFanout + 4u * W * 64u - 1u) / (4u * W * 64u));
-    const size_t lds = (2u * (ra.Tout + 4u * ra.K) + W * Xpose<EM>::WORDS + 4u * kMetaWords) * sizeof(uint32_t);
+    constexpr int PC = (int)((TMAX + 4u * kMaxFanout + 4u * W * 64u - 1u) / (4u * W * 64u));
+    if (ra.Tout > TMAX) return hipErrorInvalidValue;
+    const size_t lds =
+        (2u * (ra.Tout + 4u * ra.K) + W * Xpose<EM>::WORDS + 4u * kMetaWords + 2u * kMaxFanout) * sizeof(uint32_t);
     hipError_t e = allow_lds((const void*)k_merge_keys<EM, W, PC, MINW>, lds);
     if (e != hipSuccess) return e;
     // persistent grid: as many workgroups as fit in the LDS of `grid` CUs
@@ -436,10 +500,14 @@ hipError_t launch_merge_keys(const Phase& ph, const Bufs& b, const RoundArgs& ra
     if (ra.Tout > kToutKeys || ra.K > kMaxFanout || ra.Tout % 4 || ra.L % 4) return hipErrorInvalidValue;
     if (ph.tiles == 0) return hipSuccess;
     if (variant == 4) return launch_merge_heap(ph, b, ra, table, flip, s);
-    if (variant == 1) return launch_variant<8, 16, 1>(ph, b, ra, table, flip, grid, s);
-    if (variant == 2) return launch_variant<8, 8, 1>(ph, b, ra, table, flip, grid, s);
-    if (variant == 3) return launch_variant<8, 8, 4>(ph, b, ra, table, flip, grid, s);
-    return launch_variant<16, 8, 1>(ph, b, ra, table, flip, grid, s);
+    if (variant == 1) return launch_variant<8, 16, 1, kToutKeys>(ph, b, ra, table, flip, grid, s);
+    // shape 3 is shape 2 with registers capped for two workgroups per compute
+    // unit, which only merge tiles up to kTout2PerCU leave room for in LDS;
+    // a larger tile runs as shape 2
+    if (variant == 3 && ra.Tout <= kTout2PerCU)
+        return launch_variant<8, 8, 4, kTout2PerCU>(ph, b, ra, table, flip, grid, s);
+    if (variant == 2 || variant == 3) return launch_variant<8, 8, 1, kToutKeys>(ph, b, ra, table, flip, grid, s);
+    return launch_variant<16, 8, 1, kToutKeys>(ph, b, ra, table, flip, grid, s);
 }
 
 }  // namespace mms
