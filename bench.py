@@ -477,10 +477,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_KEYS)
     ap.add_argument("--family", default="uniform",
-                    choices=["uniform", "nearly", "sixteen", "stride64", "permutation", "sorted", "reverse"])
+                    choices=["uniform", "nearly", "sixteen", "stride64", "permutation", "sorted", "reverse",
+                             "mp_adversary"])
     ap.add_argument("--swaps", type=int, default=0, help="random pair swaps of the nearly-sorted family")
     ap.add_argument("--i32", action="store_true", help="int32 keys (signed order)")
     ap.add_argument("--pairs", action="store_true", help="stable (key, index) pairs")
+    ap.add_argument("--mergepath", action="store_true",
+                    help="time the merge-path baseline instead of the multiway sort (keys only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-sort comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop comparison")
@@ -498,14 +501,19 @@ def main():
     import paper_1702_07961_amd as mms
 
     n = args.n
-    headline = (args.family == "uniform" and not args.i32 and not args.pairs and n == N_KEYS)
+    if args.mergepath and args.pairs:
+        print("bench.py: the merge-path baseline sorts keys only", file=sys.stderr)
+        sys.exit(2)
+    headline = (args.family == "uniform" and not args.i32 and not args.pairs and not args.mergepath and n == N_KEYS)
     x_host = make_input(mmsgen, np, args.family, n, args.swaps)
-    m = measure(mms, torch, np, x_host, pairs=args.pairs, i32=args.i32, steps=args.steps, warmup=args.warmup)
+    m = measure(mms, torch, np, x_host, pairs=args.pairs, i32=args.i32, steps=args.steps, warmup=args.warmup,
+                kind="mergepath" if args.mergepath else "mms")
     copy_gbs = copy_probe(mms, torch, n)
 
     fam = args.family + (f" ({args.swaps} swaps)" if args.family == "nearly" else "")
     workload = (f"plain {'stable pair' if args.pairs else 'keys-only'} sort of {n} {fam} "
-                f"{'int32' if args.i32 else 'uint32'} keys, ascending")
+                f"{'int32' if args.i32 else 'uint32'} keys, ascending"
+                + (", merge-path baseline" if args.mergepath else ""))
     if headline:
         workload = "plain sort of 1e8 uniform uint32 keys, keys only, ascending"
     alg_bytes = m["dominant"]["alg_bytes_per_launch"]

@@ -410,6 +410,23 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
 // compiler and LDS ordering point for a wave's own scratch traffic
 __device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
+// Wait until every vector memory operation the wave has issued (loads,
+// stores, copies into LDS) is complete.
+__device__ __forceinline__ void vm_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Copy word `off` of the wave-uniform global array `base` into word `off` of
+// the wave-uniform LDS array `lds` through the memory unit (no register
+// holds it): one call per lane, lane l passing off = l, moves 64 consecutive
+// words.  The copy is complete once the wave's vector memory counter drains.
+__device__ __forceinline__ void dma_dword(const uint32_t* base, uint32_t off, uint32_t* lds) {
+    const uint64_t a = (uint64_t)(uintptr_t)base;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+    const uint32_t* ub = (const uint32_t*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(ub + off),
+                                     (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+}
+
 // Workgroup barrier for LDS traffic only.  Unlike __syncthreads() it does not
 // wait for outstanding global loads and stores, so a prefetch into registers
 // and the previous tile's stores stay in flight across it.

@@ -343,39 +343,28 @@ __global__ __launch_bounds__(W * 64) void k_merge_pairs(Phase ph, Bufs b, RoundA
         if (lane == 0) seg0[0] = 0;
     }
     lds_barrier();
-    // every thread issues the loads of all its slots of the concatenated
-    // pieces at once (slot j lies in the last piece k with seg0[k] <= j),
-    // then parks them in LDS
+    // The pieces, concatenated, go into LDS by the memory unit: 64 keys (and
+    // 64 values) per instruction, lane l's word to LDS word l of the chunk,
+    // so no register holds them and every chunk of the tile is in flight at
+    // once.  Chunks are dealt to the waves round-robin in piece order.
     {
-        constexpr uint32_t NT = W * 64u;
-        constexpr int PER = (int)((kToutPairs + NT - 1u) / NT);
-        const uint32_t filled = seg0[Kg];
-        uint32_t lk[PER], lv[PER];
-#pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            const uint32_t j = (uint32_t)r * NT + threadIdx.x;
-            lk[r] = 0u;
-            lv[r] = 0u;
-            if (j < filled) {
-                uint32_t lo = 0, hi = Kg;
-                while (hi - lo > 1u) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (seg0[mid] <= j) lo = mid;
-                    else hi = mid;
+        uint32_t cbase = 0;   // chunks of the earlier pieces
+        for (uint32_t k = 0; k < Kg; ++k) {
+            const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)seg0[k]);
+            const uint32_t s1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)seg0[k + 1]);
+            const uint32_t st = (uint32_t)__builtin_amdgcn_readfirstlane((int)start[k]);
+            const uint32_t nch = s1 > s0 ? (s1 - s0 + 63u) >> 6 : 0u;
+            const uint64_t run0 = gb + (uint64_t)k * L + st;   // the piece's first element
+            for (uint32_t c = ((uint32_t)wave + W - cbase % W) % W; c < nch; c += W) {
+                const uint32_t j0 = s0 + 64u * c;
+                if (j0 + (uint32_t)lane < s1) {
+                    dma_dword(src_k + run0 + 64u * c, (uint32_t)lane, Xk + j0);
+                    dma_dword(src_v + run0 + 64u * c, (uint32_t)lane, Xv + j0);
                 }
-                const uint64_t src = gb + (uint64_t)lo * L + start[lo] + (j - seg0[lo]);
-                lk[r] = gptr(src_k)[src];
-                lv[r] = gptr(src_v)[src];
             }
+            cbase += nch;
         }
-#pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            const uint32_t j = (uint32_t)r * NT + threadIdx.x;
-            if (j < filled) {
-                Xk[j] = lk[r];
-                Xv[j] = lv[r];
-            }
-        }
+        vm_drain();
     }
     lds_barrier();
 

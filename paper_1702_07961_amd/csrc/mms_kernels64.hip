@@ -218,36 +218,31 @@ __global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundA
     }
     lds_barrier();
     {
-        // every thread issues the loads of all its slots at once (slot j lies
-        // in the last piece k with seg0[k] <= j), then parks them in LDS
-        constexpr int PER = (int)((kTout64Keys + NT - 1u) / NT);
-        const uint32_t filled = seg0[Kg];
-        uint64_t lk[PER], lv[PER];
-#pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            const uint32_t j = (uint32_t)r * NT + threadIdx.x;
-            lk[r] = 0;
-            lv[r] = 0;
-            if (j < filled) {
-                uint32_t lo = 0, hi = Kg;
-                while (hi - lo > 1u) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (seg0[mid] <= j) lo = mid;
-                    else hi = mid;
+        // the pieces, concatenated, go into LDS by the memory unit: 64 words
+        // (32 elements) of keys (and of values) per instruction, no register
+        // holding them, every chunk in flight at once; chunks are dealt to
+        // the waves round-robin in piece order
+        uint32_t cbase = 0;
+        for (uint32_t k = 0; k < Kg; ++k) {
+            const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)seg0[k]);
+            const uint32_t s1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)seg0[k + 1]);
+            const uint32_t st = (uint32_t)__builtin_amdgcn_readfirstlane((int)start[k]);
+            const uint32_t w0 = 2u * s0, w1 = s1 > s0 ? 2u * s1 : w0;   // LDS words of the piece
+            const uint32_t nch = (w1 - w0 + 63u) >> 6;
+            const uint64_t run0 = 2u * (gb + (uint64_t)k * L + st);   // the piece's first word
+            for (uint32_t c = ((uint32_t)wave + W - cbase % W) % W; c < nch; c += W) {
+                const uint32_t j0 = w0 + 64u * c;
+                if (j0 + (uint32_t)lane < w1) {
+                    dma_dword(reinterpret_cast<const uint32_t*>(src_k) + run0 + 64u * c, (uint32_t)lane,
+                              reinterpret_cast<uint32_t*>(Xk) + j0);
+                    if constexpr (PAIRS)
+                        dma_dword(reinterpret_cast<const uint32_t*>(src_v) + run0 + 64u * c, (uint32_t)lane,
+                                  reinterpret_cast<uint32_t*>(Xv) + j0);
                 }
-                const uint64_t sp = gb + (uint64_t)lo * L + start[lo] + (j - seg0[lo]);
-                lk[r] = gptr64(src_k)[sp];
-                if constexpr (PAIRS) lv[r] = gptr64(src_v)[sp];
             }
+            cbase += nch;
         }
-#pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            const uint32_t j = (uint32_t)r * NT + threadIdx.x;
-            if (j < filled) {
-                Xk[j] = lk[r];
-                if constexpr (PAIRS) Xv[j] = lv[r];
-            }
-        }
+        vm_drain();
     }
     lds_barrier();
 

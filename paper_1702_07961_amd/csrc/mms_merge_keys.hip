@@ -108,9 +108,6 @@ __device__ __forceinline__ void split_from_rows(const uint32_t* rows, const Tile
     }
 }
 
-// Wait until every vector memory operation the wave has issued is complete.
-__device__ __forceinline__ void vm_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
-
 // Rows t and t+1 of the split table (2K consecutive words; the table has a
 // row past the last tile) copied into LDS by the memory unit, one word per
 // lane, without passing through registers.  The copy is complete once the

@@ -271,20 +271,29 @@ uint64_t meta_bytes(uint64_t segs, uint64_t ntasks, uint64_t max_round_tiles, ui
            (rounds ? align_up((max_round_tiles + 1) * K * 4) : 0);
 }
 
+// Size class of a request: sizes within one class differ by less than a
+// factor of 16, so a batch's requests finish at about the same time and a
+// small request never waits for a large one's sort.
+uint32_t size_class(uint64_t n) { return ceil_log2(n) / 4u; }
+
 // The next batch: the oldest admitted request and, in admission order, every
-// later one of the same kind within the batch limits and the metadata slot.
-// The batch is planned with the tuning of the candidates' total (capped by
-// the batch limits), as a segmented sort of them would be.
+// later one of the same kind and size class within the batch limits and the
+// metadata slot (the others form later batches, which the other streams run
+// at the same time).  The batch is planned with the tuning of the
+// candidates' total (capped by the batch limits), as a segmented sort of them
+// would be.
 Batch form_batch(mms_server* s, int stream, int slot) {
     Batch b;
     b.id = s->next_batch++;
     b.stream = stream;
     b.slot = slot;
-    const uint32_t kind = s->reqs[s->admitted.front()].r.flags;
+    const Req& head = s->reqs[s->admitted.front()];
+    const uint32_t kind = head.r.flags;
+    const uint32_t cls = size_class(head.r.n);
     uint64_t cand_keys = 0, cand_n = 0;
     for (uint64_t t : s->admitted) {
         const Req& q = s->reqs[t];
-        if (q.r.flags != kind || cand_n >= s->cfg.max_batch_requests) continue;
+        if (q.r.flags != kind || size_class(q.r.n) != cls || cand_n >= s->cfg.max_batch_requests) continue;
         if (cand_n && cand_keys + q.r.n > s->cfg.max_batch_keys) continue;
         cand_keys += q.r.n;
         ++cand_n;
@@ -295,7 +304,7 @@ Batch form_batch(mms_server* s, int stream, int slot) {
     std::deque<uint64_t> rest;
     for (uint64_t t : s->admitted) {
         Req& q = s->reqs[t];
-        bool take = q.r.flags == kind && b.tickets.size() < s->cfg.max_batch_requests &&
+        bool take = q.r.flags == kind && size_class(q.r.n) == cls && b.tickets.size() < s->cfg.max_batch_requests &&
                     keys + q.r.n <= s->cfg.max_batch_keys;
         if (take) {
             mine.assign(phases.size(), 0);

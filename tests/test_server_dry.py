@@ -162,6 +162,26 @@ def test_batches_hold_one_kind(mms):
         assert s.stats()["used_bytes"] == 0
 
 
+def test_batches_hold_one_size_class(mms):
+    """A batch holds requests of one size class (ceil(log2 n) // 4: sizes
+    within a factor of 16), so small requests never wait in a batch for a
+    large one's sort."""
+    def cls(n):
+        return (max(n, 1) - 1).bit_length() // 4
+    with make(mms, max_requests=64, budget=1 << 26) as s:
+        sizes = [100, 900, 5000, 20_000, 70_000, 300_000, 1 << 20]
+        tickets = [(s.submit(n=n), n) for n in sizes * 4]
+        batches = {}
+        for t, n in tickets:
+            r = s.wait(t, 5000)
+            assert r.status == 0
+            batches.setdefault(r.batch, set()).add(cls(n))
+        assert all(len(v) == 1 for v in batches.values())
+        assert len(batches) >= len({cls(n) for n in sizes})
+        for t, _ in tickets:
+            s.release(t)
+
+
 def test_shutdown_fails_queued_requests(mms):
     s = make(mms, max_requests=1)
     a = s.submit(n=100)
