@@ -479,11 +479,11 @@ __device__ __forceinline__ void block_sort_keys(uint32_t (&m)[EM], uint32_t* scr
     }
     if constexpr (EM == 8) {                             // index bit 2 = lane bit 0
         const uint32_t keep_max = (ul & 1u) ? ~0u : 0u;
+        uint32_t o[EM];   // all exchanges first: no wait states between a write and its exchange
 #pragma unroll
-        for (int e = 0; e < EM; ++e) {
-            const uint32_t o = (uint32_t)__builtin_amdgcn_mov_dpp((int)m[e], 0xB1, 0xF, 0xF, false);
-            m[e] = med3_u32(m[e], o, keep_max);
-        }
+        for (int e = 0; e < EM; ++e) o[e] = (uint32_t)__builtin_amdgcn_mov_dpp((int)m[e], 0xB1, 0xF, 0xF, false);
+#pragma unroll
+        for (int e = 0; e < EM; ++e) m[e] = med3_u32(m[e], o[e], keep_max);
     }
 #pragma unroll
     for (int c = 0; c < EM / 4; ++c) {                   // index bits 1..0
@@ -538,6 +538,22 @@ struct GlobalSinkKeys {
     }
 };
 
+// Number of block positions k = 64 e + lane with a_k <= b_k.  a is
+// non-decreasing and b non-increasing in k, so those positions are a prefix
+// of the block: a binary search over the registers, testing each one's last
+// lane, finds the register the prefix ends in (log2 EM + 1 ballots instead of
+// EM).  Registers below LO are known to hold only positions of the prefix.
+template <int LO, int HI, int EM>
+__device__ __forceinline__ uint32_t prefix_len(const uint32_t (&a)[EM], const uint32_t (&b)[EM]) {
+    if constexpr (HI - LO == 1) {
+        return (uint32_t)LO * 64u + (uint32_t)__popcll(__ballot(a[LO] <= b[LO]));
+    } else {
+        constexpr int MID = (LO + HI) / 2;
+        if (__ballot(a[MID - 1] <= b[MID - 1]) >> 63) return prefix_len<MID, HI, EM>(a, b);
+        return prefix_len<LO, MID, EM>(a, b);
+    }
+}
+
 // Merge outputs [d0, d1) of A = X[aA, aA+la) and B = X[aB, aB+lb) (keys),
 // blocks of N = 64*EM as in merge_pair_range; out_base + d0 must be a
 // multiple of 4.
@@ -581,10 +597,8 @@ __device__ __forceinline__ void merge_pair_range_keys(const uint32_t* X, uint32_
                 b[e] = Bp[-(e * kWave)];
             }
 #pragma unroll
-            for (int e = 0; e < EM; ++e) {
-                m[e] = min(a[e], b[e]);
-                u += (uint32_t)__popcll(__ballot(a[e] <= b[e]));
-            }
+            for (int e = 0; e < EM; ++e) m[e] = min(a[e], b[e]);
+            u = prefix_len<0, EM, EM>(a, b);
         } else {
             // near the end of a run: the same reads, then the sentinel for
             // every position past the run's end, with no branch per element.
@@ -606,11 +620,11 @@ __device__ __forceinline__ void merge_pair_range_keys(const uint32_t* X, uint32_
 #pragma unroll
             for (int e = 0; e < EM; ++e) {
                 const uint32_t k = (uint32_t)e * kWave + (uint32_t)lane;
-                const uint32_t av = k < ra ? a[e] : kSentKey;
-                const uint32_t bv = N - 1u - k < rb ? b[e] : kSentKey;
-                m[e] = min(av, bv);
-                u += (uint32_t)__popcll(__ballot(av <= bv));
+                a[e] = k < ra ? a[e] : kSentKey;          // still non-decreasing in k
+                b[e] = N - 1u - k < rb ? b[e] : kSentKey;  // still non-increasing in k
+                m[e] = min(a[e], b[e]);
             }
+            u = prefix_len<0, EM, EM>(a, b);
         }
         block_sort_keys<EM>(m, scr, lane);
         out.template put_block<EM>(out_base + o, min(N, d1 - o), m, lane);
