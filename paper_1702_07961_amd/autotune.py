@@ -95,7 +95,7 @@ def tune_pairs(mms, torch, x_all, min_log2: int, max_log2: int, reps: int, log=p
         kk = ok.to(torch.int64) & 0xFFFFFFFF
         if not bool((kk[1:] >= kk[:-1]).all()):
             raise RuntimeError(f"tuned key-value sort of 2^{b} is not sorted")
-        entries.append({"max_log2_n": b, "fanout": K, "merge_tile": 4096, "variant": 0, "base": base,
+        entries.append({"max_log2_n": b, "fanout": K, "merge_tile": 3840, "variant": 0, "base": base,
                         "ms": round(ms, 5), "gpairs_per_s": round(n / ms / 1e6, 3)})
         log(f"pairs 2^{b}: K={K} base={base} {ms:.4f} ms ({n / ms / 1e6:.2f} Gpairs/s)")
     return entries

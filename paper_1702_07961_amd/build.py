@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmms.so")
 
-SOURCES = ["mms_kernels.hip", "mms_merge_keys.hip", "mms_merge_heap.hip", "mms_kernels64.hip", "mms_mergepath.hip", "mms_noalloc.hip", "mms_api.cpp", "mms_server.cpp"]
+SOURCES = ["mms_kernels.hip", "mms_merge_keys.hip", "mms_merge_pairs.hip", "mms_merge_heap.hip", "mms_kernels64.hip", "mms_mergepath.hip", "mms_noalloc.hip", "mms_api.cpp", "mms_server.cpp"]
 ARCH = "gfx950"
 
 COMMON = [

@@ -407,8 +407,12 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
     return q;
 }
 
-// compiler and LDS ordering point for a wave's own scratch traffic
-__device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+// Ordering point for a wave's own LDS traffic.  The LDS performs a wave's
+// operations in the order the wave issues them, so a read issued after the
+// wave's own writes returns what they wrote without waiting for them to
+// complete (the compiler's memory model emits no wait for a fence at
+// wavefront scope either); only the compiler must keep the order.
+__device__ __forceinline__ void lds_wave_sync() { asm volatile("" ::: "memory"); }
 
 // Wait until every vector memory operation the wave has issued (loads,
 // stores, copies into LDS) is complete.

@@ -1,0 +1,332 @@
+// Key-value building blocks: a (key, tag) pair as one 64-bit word.
+//
+// The merge and base case of the key-value sort order the pairs (key, tag),
+// tag being an element's slot in the tile as loaded, which is the stable
+// order (§4.2 sorts blocks with bitonic networks, which are not stable on
+// keys alone); the values stay in LDS where they were loaded and are
+// gathered by tag when a tile is stored.  The pair is packed into the
+// mantissa of a positive normal double with a fixed exponent:
+//   bits 63..52  0x400 (sign 0, biased exponent 1024)
+//   bits 51..20  key
+//   bits 19..0   tag (< 2^16 here; the sentinel's is 0xFFFFF)
+// Doubles of one sign and exponent order like their mantissas, so the 64-bit
+// float min and max (one full-rate instruction each, exact, no rounding) are
+// the compare-exchange of the pairs, and the sentinel (key 0xFFFFFFFF, tag
+// 0xFFFFF) is above every real element.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mms_device.h"
+
+namespace mms {
+
+constexpr uint32_t kKtExp = 0x400u << 20;   // sign and exponent in the high word
+
+__device__ __forceinline__ double kt_join(uint32_t hi, uint32_t lo) {
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ uint32_t kt_hi(double x) { return (uint32_t)(__builtin_bit_cast(uint64_t, x) >> 32); }
+__device__ __forceinline__ uint32_t kt_lo(double x) { return (uint32_t)__builtin_bit_cast(uint64_t, x); }
+
+__device__ __forceinline__ double kt_pack(uint32_t key, uint32_t tag) {
+    // high word: exponent | key >> 12; low word: key << 20 | tag
+    return kt_join(__builtin_amdgcn_alignbit(0x400u, key, 12u), (key << 20) | tag);
+}
+__device__ __forceinline__ uint32_t kt_key(double x) { return __builtin_amdgcn_alignbit(kt_hi(x), kt_lo(x), 20u); }
+__device__ __forceinline__ uint32_t kt_tag(double x) { return kt_lo(x) & 0xFFFFFu; }
+__device__ __forceinline__ double kt_sentinel() { return kt_join(kKtExp | 0xFFFFFu, 0xFFFFFFFFu); }
+
+// min and max as single instructions (the library's fmin would first
+// quieten possible signalling NaNs, which these values never are)
+__device__ __forceinline__ double kt_min(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double kt_max(double a, double b) {
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ void cex_kt(double& lo, double& hi) {
+    const double a = lo, b = hi;
+    lo = kt_min(a, b);
+    hi = kt_max(a, b);
+}
+
+template <int EM>
+__device__ __forceinline__ void reg_stages_kt(double (&m)[EM]) {
+#pragma unroll
+    for (int d = EM / 2; d >= 1; d >>= 1) {
+#pragma unroll
+        for (int e = 0; e < EM; ++e)
+            if ((e & d) == 0) cex_kt(m[e], m[e | d]);
+    }
+}
+
+// One transpose step of block_sort_kt for one 32-bit half of every element:
+// write the half at wr(e), read it back at rd(e).  The LDS performs a wave's
+// operations in order, so the second half's writes may follow the first
+// half's reads into the same scratch without a wait.
+template <int EM, class Wr, class Rd>
+__device__ __forceinline__ void xpose_half(uint32_t (&h)[EM], uint32_t* scr, Wr wr, Rd rd) {
+#pragma unroll
+    for (int e = 0; e < EM; ++e) scr[wr(e)] = h[e];
+    lds_wave_sync();
+#pragma unroll
+    for (int e = 0; e < EM; ++e) h[e] = scr[rd(e)];
+    lds_wave_sync();
+}
+
+// Sort the bitonic block of N = 64*EM pairs held in layout S (register =
+// index bits above 6, lane = bits 5..0) into layout F (register 4c+j =
+// position c*256 + 4*lane + j), with the index moves of block_sort_keys and
+// the same conflict-free scratch pattern, each transpose done once for the
+// high and once for the low words.
+template <int EM>
+__device__ __forceinline__ void block_sort_kt(double (&m)[EM], uint32_t* scr, int lane) {
+    static_assert(EM == 8, "64x8-pair blocks");
+    constexpr uint32_t RS = Xpose<EM>::RS;
+    const uint32_t ul = (uint32_t)lane;
+    asm volatile("" ::: "memory");                       // the previous block's scratch reads come first
+    reg_stages_kt<EM>(m);                                // index bits 8..6
+    uint32_t hi[EM], lo[EM];
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+        hi[e] = kt_hi(m[e]);
+        lo[e] = kt_lo(m[e]);
+    }
+    const uint32_t tb = (ul >> 3) * RS + (ul & 7u);      // lane = (bits 8..6, bits 2..0)
+    auto s_at = [&](int e) { return (uint32_t)e * RS + ul; };
+    auto t_at = [&](int e) { return tb + (uint32_t)e * 8u; };
+    xpose_half<EM>(hi, scr, s_at, t_at);
+    xpose_half<EM>(lo, scr, s_at, t_at);
+#pragma unroll
+    for (int e = 0; e < EM; ++e) m[e] = kt_join(hi[e], lo[e]);
+    reg_stages_kt<EM>(m);                                // index bits 5..3
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+        hi[e] = kt_hi(m[e]);
+        lo[e] = kt_lo(m[e]);
+    }
+    const uint32_t fb = (ul >> 4) * RS + 4u * (ul & 15u);
+    auto to_f = [&](uint32_t (&h)[EM]) {
+#pragma unroll
+        for (int e = 0; e < EM; ++e) scr[t_at(e)] = h[e];
+        lds_wave_sync();
+#pragma unroll
+        for (int c = 0; c < EM / 4; ++c) {
+            const uint4 v = *reinterpret_cast<const uint4*>(scr + fb + (uint32_t)c * 4u * RS);
+            h[4 * c + 0] = v.x;
+            h[4 * c + 1] = v.y;
+            h[4 * c + 2] = v.z;
+            h[4 * c + 3] = v.w;
+        }
+        lds_wave_sync();
+    };
+    to_f(hi);
+    to_f(lo);
+    // index bit 2 = lane bit 0: lanes l and l ^ 1 meet, the odd lane keeps
+    // the larger pair
+    const bool keep_max = (ul & 1u) != 0;
+    uint32_t oh[EM], ol[EM];
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+        oh[e] = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi[e], 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+        ol[e] = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo[e], 0xB1, 0xF, 0xF, false);
+    }
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+        const double a = kt_join(hi[e], lo[e]), o = kt_join(oh[e], ol[e]);
+        const double mn = kt_min(a, o), mx = kt_max(a, o);
+        m[e] = keep_max ? mx : mn;
+    }
+#pragma unroll
+    for (int c = 0; c < EM / 4; ++c) {                   // index bits 1..0
+        cex_kt(m[4 * c + 0], m[4 * c + 2]);
+        cex_kt(m[4 * c + 1], m[4 * c + 3]);
+        cex_kt(m[4 * c + 0], m[4 * c + 1]);
+        cex_kt(m[4 * c + 2], m[4 * c + 3]);
+    }
+}
+
+// Number of block positions k with a_k < b_k (a increasing and b
+// decreasing in k, so they form a prefix): a binary search over the
+// registers' last lanes, as prefix_len does for keys.
+template <int LO, int HI, int EM>
+__device__ __forceinline__ uint32_t prefix_len_kt(const double (&a)[EM], const double (&b)[EM]) {
+    if constexpr (HI - LO == 1) {
+        return (uint32_t)LO * 64u + (uint32_t)__popcll(__ballot(a[LO] < b[LO]));
+    } else {
+        constexpr int MID = (LO + HI) / 2;
+        if (__ballot(a[MID - 1] < b[MID - 1]) >> 63) return prefix_len_kt<MID, HI, EM>(a, b);
+        return prefix_len_kt<LO, MID, EM>(a, b);
+    }
+}
+
+// LDS sources of a merge level.  Level 0 reads the keys as loaded, each
+// element's tag being its own slot; later levels read keys and 16-bit tags.
+struct KtSrcLoaded {
+    const uint32_t* k;
+    __device__ __forceinline__ double at(uint32_t i) const { return kt_pack(k[i], i); }
+    // pairs i .. i+3 (i a multiple of 4)
+    __device__ __forceinline__ void at4(uint32_t i, double* r) const {
+        const uint4 v = *reinterpret_cast<const uint4*>(k + i);
+        r[0] = kt_pack(v.x, i);
+        r[1] = kt_pack(v.y, i + 1u);
+        r[2] = kt_pack(v.z, i + 2u);
+        r[3] = kt_pack(v.w, i + 3u);
+    }
+};
+struct KtSrcTagged {
+    const uint32_t* k;
+    const uint16_t* t;
+    __device__ __forceinline__ double at(uint32_t i) const { return kt_pack(k[i], t[i]); }
+    __device__ __forceinline__ void at4(uint32_t i, double* r) const {
+        const uint4 v = *reinterpret_cast<const uint4*>(k + i);
+        const uint2 w = *reinterpret_cast<const uint2*>(t + i);
+        r[0] = kt_pack(v.x, w.x & 0xFFFFu);
+        r[1] = kt_pack(v.y, w.x >> 16);
+        r[2] = kt_pack(v.z, w.y & 0xFFFFu);
+        r[3] = kt_pack(v.w, w.y >> 16);
+    }
+};
+
+// Sinks for a sorted block in layout F: block position t = c*256 + 4*lane +
+// j goes to pos0 + t when t < cnt (pos0 a multiple of 4).
+struct KtSinkLds {
+    uint32_t* k;
+    uint16_t* t;
+    template <int EM>
+    __device__ __forceinline__ void put_block(uint32_t pos0, uint32_t cnt, const double (&m)[EM], int lane) const {
+#pragma unroll
+        for (int c = 0; c < EM / 4; ++c) {
+            const uint32_t p = (uint32_t)c * 256u + 4u * (uint32_t)lane;
+            const double* r = m + 4 * c;
+            if (p + 4u <= cnt) {
+                *reinterpret_cast<uint4*>(k + pos0 + p) = make_uint4(kt_key(r[0]), kt_key(r[1]), kt_key(r[2]), kt_key(r[3]));
+                // two 16-bit tags per word: the low halves of the low words
+                *reinterpret_cast<uint2*>(t + pos0 + p) =
+                    make_uint2(__builtin_amdgcn_perm(kt_lo(r[1]), kt_lo(r[0]), 0x05040100u),
+                               __builtin_amdgcn_perm(kt_lo(r[3]), kt_lo(r[2]), 0x05040100u));
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (p + (uint32_t)j < cnt) {
+                        k[pos0 + p + j] = kt_key(r[j]);
+                        t[pos0 + p + j] = (uint16_t)kt_lo(r[j]);
+                    }
+                }
+            }
+        }
+    }
+};
+// The last level: keys to memory (undoing the signed-key mapping) and each
+// pair's value, gathered from the tile's value slots by its tag.
+struct KtSinkGlobal {
+    uint32_t* k;         // tile output base
+    uint32_t* v;
+    const uint32_t* V;   // LDS values, by slot
+    uint32_t flip;
+    uint32_t lim;        // positions >= lim are not stored
+    bool vec;            // k and v are 16-byte aligned
+    template <int EM>
+    __device__ __forceinline__ void put_block(uint32_t pos0, uint32_t cnt, const double (&m)[EM], int lane) const {
+        const uint32_t c_lim = min(cnt, lim > pos0 ? lim - pos0 : 0u);
+        gu32* gk = gptr(k);
+        gu32* gv = gptr(v);
+#pragma unroll
+        for (int c = 0; c < EM / 4; ++c) {
+            const uint32_t p = (uint32_t)c * 256u + 4u * (uint32_t)lane;
+            const double* r = m + 4 * c;
+            if (vec && p + 4u <= c_lim) {
+                *reinterpret_cast<gu32x4*>(gk + pos0 + p) =
+                    u32x4{kt_key(r[0]) ^ flip, kt_key(r[1]) ^ flip, kt_key(r[2]) ^ flip, kt_key(r[3]) ^ flip};
+                *reinterpret_cast<gu32x4*>(gv + pos0 + p) =
+                    u32x4{V[kt_tag(r[0])], V[kt_tag(r[1])], V[kt_tag(r[2])], V[kt_tag(r[3])]};
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (p + (uint32_t)j < c_lim) {
+                        gk[pos0 + p + j] = kt_key(r[j]) ^ flip;
+                        gv[pos0 + p + j] = V[kt_tag(r[j])];
+                    }
+                }
+            }
+        }
+    }
+};
+
+// Merge outputs [d0, d1) of A = X[aA, aA+la) and B = X[aB, aB+lb) in blocks
+// of N = 64*EM pairs, the key-value form of merge_pair_range_keys: A holds
+// the smaller tags, so the split on keys with A first on ties is the split
+// of the pair order.  out_base + d0 must be a multiple of 4.
+template <int EM, class Src, class Sink>
+__device__ __forceinline__ void merge_pair_range_kt(const Src& X, uint32_t aA, uint32_t la, uint32_t aB, uint32_t lb,
+                                                    uint32_t d0, uint32_t d1, const Sink& out, uint32_t out_base,
+                                                    uint32_t* scr, int lane) {
+    constexpr uint32_t N = (uint32_t)kWave * EM;
+    if (la == 0 || lb == 0) {
+        // one run is empty: the other is already in order; move it in the
+        // block layout (reads past the run stay in the caller's LDS and are
+        // not stored)
+        const uint32_t a0 = lb == 0 ? aA : aB;
+        for (uint32_t o = d0; o < d1; o += N) {
+            double m[EM];
+#pragma unroll
+            for (int c = 0; c < EM / 4; ++c) X.at4(a0 + o + (uint32_t)c * 256u + 4u * (uint32_t)lane, m + 4 * c);
+            out.template put_block<EM>(out_base + o, min(N, d1 - o), m, lane);
+        }
+        return;
+    }
+    uint32_t p = lds_corank2(X.k, aA, la, aB, lb, d0, lane);
+    uint32_t q = d0 - p;
+    for (uint32_t o = d0; o < d1; o += N) {
+        double m[EM];
+        uint32_t u;
+        if (p + N <= la && q + N <= lb) {
+            const uint32_t ia = aA + p + (uint32_t)lane;
+            const uint32_t ib = aB + q + (N - 1u) - (uint32_t)lane;
+            double a[EM], b[EM];
+#pragma unroll
+            for (int e = 0; e < EM; ++e) {
+                a[e] = X.at(ia + (uint32_t)e * kWave);
+                b[e] = X.at(ib - (uint32_t)e * kWave);
+            }
+#pragma unroll
+            for (int e = 0; e < EM; ++e) m[e] = kt_min(a[e], b[e]);
+            u = prefix_len_kt<0, EM, EM>(a, b);
+        } else {
+            // near the end of a run: the same reads, then the sentinel for
+            // every position past a run's end.  Those reads stay below the
+            // end of the last run plus N, inside the caller's LDS; what they
+            // return is discarded.  The sentinel is above every pair, so
+            // the cursors only pass a run's end in the tile's last block.
+            const uint32_t pc = min(p, la), qc = min(q, lb);
+            const uint32_t ia = aA + pc + (uint32_t)lane;
+            const uint32_t ib = aB + qc + (N - 1u) - (uint32_t)lane;
+            const uint32_t ra = la - pc, rb = lb - qc;
+            double a[EM], b[EM];
+#pragma unroll
+            for (int e = 0; e < EM; ++e) {
+                a[e] = X.at(ia + (uint32_t)e * kWave);
+                b[e] = X.at(ib - (uint32_t)e * kWave);
+            }
+#pragma unroll
+            for (int e = 0; e < EM; ++e) {
+                const uint32_t k = (uint32_t)e * kWave + (uint32_t)lane;
+                a[e] = k < ra ? a[e] : kt_sentinel();
+                b[e] = N - 1u - k < rb ? b[e] : kt_sentinel();
+                m[e] = kt_min(a[e], b[e]);
+            }
+            u = prefix_len_kt<0, EM, EM>(a, b);
+        }
+        block_sort_kt<EM>(m, scr, lane);
+        out.template put_block<EM>(out_base + o, min(N, d1 - o), m, lane);
+        p = (uint32_t)__builtin_amdgcn_readfirstlane((int)(p + u));
+        q = (uint32_t)__builtin_amdgcn_readfirstlane((int)(q + N - u));
+    }
+}
+
+}  // namespace mms

@@ -20,10 +20,9 @@ constexpr int base_w(int shape) { return kShapeW[shape]; }
 constexpr uint32_t base_tile(int shape) { return 64u * (uint32_t)base_e(shape) * (uint32_t)base_w(shape); }
 constexpr uint32_t kT1 = 2048;
 static_assert(base_tile(0) == kT1 && base_tile(1) == kT1 && base_tile(2) == kT1, "the smallest tile");
-constexpr int kEM = 8;      // merge block of the key-value path
 constexpr int kW3 = 8;      // waves of the key-value merge
 constexpr uint32_t kToutKeys = 8192;   // largest keys-only merge tile
-constexpr uint32_t kToutPairs = 4096;
+constexpr uint32_t kToutPairs = 3840;   // two key-value merge workgroups per compute unit
 constexpr uint32_t kMaxFanout = 16;
 
 // The buffers of one segment: its input, its output and its ping-pong

@@ -281,109 +281,6 @@ __global__ __launch_bounds__(256) void k_corank_queries(const uint32_t* __restri
 }
 
 // ===========================================================================
-// Key-value merge (§4.2, §7): one workgroup per output tile of a round.  The
-// tile's pieces of its group's K runs, bounded by the split indices of its
-// first and last output, are loaded into LDS back to back, merged pairwise
-// level by level inside LDS (log2 K levels), and the last level is written to
-// memory.  A group holding a single run is copied.
-// ===========================================================================
-template <int W>
-__global__ __launch_bounds__(W * 64) void k_merge_pairs(Phase ph, Bufs b, RoundArgs ra,
-                                                        const uint32_t* __restrict__ table, uint32_t flip) {
-    constexpr bool P = true;
-    const uint32_t Tout = ra.Tout, K = ra.K;
-    const uint64_t L = ra.L;
-    extern __shared__ uint32_t smem[];
-    uint32_t* Xk = smem;
-    uint32_t* Yk = smem + Tout;
-    uint32_t* Xv = smem + 2 * Tout;
-    uint32_t* Yv = smem + 3 * Tout;
-    uint32_t* seg0 = smem + 4 * Tout;             // [kMaxFanout + 1]
-    uint32_t* start = seg0 + kMaxFanout + 1;      // [kMaxFanout]
-
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
-    const uint64_t t = blockIdx.x;
-    const TileRef tr = tile_ref(ph, b, t);
-    const uint32_t* src_k = tr.src_k;
-    const uint32_t* src_v = tr.src_v;
-    uint32_t* dst_k = tr.dst_k;
-    uint32_t* dst_v = tr.dst_v;
-    const uint32_t flip_out = tr.final_pass ? flip : 0u;
-    const uint32_t grp = tr.local / (uint32_t)ra.tpg;
-    const uint64_t i = tr.local - (uint64_t)grp * ra.tpg;
-    const uint64_t span = (uint64_t)K * L;
-    const uint64_t gb = (uint64_t)grp * span;
-    const uint64_t glen = min(span, tr.n - gb);
-    const uint32_t Kg = (uint32_t)((glen + L - 1) / L);
-    const uint64_t obeg = i * (uint64_t)Tout;
-    const uint32_t cnt = (uint32_t)min<uint64_t>(Tout, glen - obeg);
-    const uint64_t obase = gb + obeg;
-
-    if (Kg == 1) {   // a lone run: its tile is already in order
-        for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
-            dst_k[obase + j] = src_k[obase + j] ^ flip_out;
-            dst_v[obase + j] = src_v[obase + j];
-        }
-        return;
-    }
-    if (wave == 0) {   // lane k < Kg: piece k; piece starts by a row prefix sum
-        uint32_t len = 0;
-        if ((uint32_t)lane < Kg) {
-            const uint32_t k = (uint32_t)lane;
-            const uint64_t nk = min(L, glen - (uint64_t)k * L);
-            // the clamps only guard memory safety; exact splits never trigger them
-            const uint32_t s = i == 0 ? 0u : min(table[t * K + k], (uint32_t)nk);
-            const uint32_t e = (obeg + Tout >= glen) ? (uint32_t)nk : min(table[(t + 1) * K + k], (uint32_t)nk);
-            start[k] = s;
-            len = e > s ? e - s : 0u;
-        }
-        const uint32_t incl = row16_incl_sum(len);
-        if ((uint32_t)lane < Kg) seg0[lane + 1] = min(incl, cnt);
-        if (lane == 0) seg0[0] = 0;
-    }
-    lds_barrier();
-    // The pieces, concatenated, go into LDS by the memory unit: 64 keys (and
-    // 64 values) per instruction, lane l's word to LDS word l of the chunk,
-    // so no register holds them and every chunk of the tile is in flight at
-    // once.  Chunks are dealt to the waves round-robin in piece order.
-    {
-        uint32_t cbase = 0;   // chunks of the earlier pieces
-        for (uint32_t k = 0; k < Kg; ++k) {
-            const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)seg0[k]);
-            const uint32_t s1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)seg0[k + 1]);
-            const uint32_t st = (uint32_t)__builtin_amdgcn_readfirstlane((int)start[k]);
-            const uint32_t nch = s1 > s0 ? (s1 - s0 + 63u) >> 6 : 0u;
-            const uint64_t run0 = gb + (uint64_t)k * L + st;   // the piece's first element
-            for (uint32_t c = ((uint32_t)wave + W - cbase % W) % W; c < nch; c += W) {
-                const uint32_t j0 = s0 + 64u * c;
-                if (j0 + (uint32_t)lane < s1) {
-                    dma_dword(src_k + run0 + 64u * c, (uint32_t)lane, Xk + j0);
-                    dma_dword(src_v + run0 + 64u * c, (uint32_t)lane, Xv + j0);
-                }
-            }
-            cbase += nch;
-        }
-        vm_drain();
-    }
-    lds_barrier();
-
-    for (uint32_t lvl = 0; (1u << lvl) < Kg; ++lvl) {
-        const bool last = (2u << lvl) >= Kg;
-        const LdsKV32 X{Xk, Xv};
-        if (last) {
-            GlobalSinkLim<P> out{dst_k + obase, dst_v + obase, flip_out, cnt};
-            merge_level<kEM>(X, seg0, Kg, lvl, cnt, out, wave, W, lane);
-        } else {
-            merge_level<kEM>(X, seg0, Kg, lvl, cnt, LdsKV32{Yk, Yv}, wave, W, lane);
-        }
-        lds_barrier();
-        uint32_t* tmp = Xk; Xk = Yk; Yk = tmp;
-        tmp = Xv; Xv = Yv; Yv = tmp;
-    }
-}
-
-// ===========================================================================
 // Streaming copy: each lane moves kCopyUnroll 16-byte chunks per trip, all
 // loads in flight before the stores, with non-temporal loads and stores (the
 // data is touched once).  Chunk u of a trip is 256 chunks after chunk u-1, so
@@ -482,17 +379,6 @@ hipError_t launch_corank_queries(const uint32_t* keys, uint64_t n, uint64_t L, u
     const uint64_t blocks = (nq + 3) / 4;
     hipLaunchKernelGGL(k_corank_queries, dim3((unsigned)blocks), dim3(256), 0, s, keys, n, L, K, group, rank, nq,
                        split, flip);
-    return hipGetLastError();
-}
-
-hipError_t launch_merge_pairs(const Phase& ph, const Bufs& b, const RoundArgs& ra, const uint32_t* table,
-                              uint32_t flip, hipStream_t s) {
-    if (ph.tiles == 0) return hipSuccess;
-    if (ra.Tout > kToutPairs) return hipErrorInvalidValue;   // the loader covers kToutPairs slots
-    const size_t lds = (4u * ra.Tout + 2u * kMaxFanout + 8u) * sizeof(uint32_t);
-    hipError_t e = allow_lds((const void*)k_merge_pairs<kW3>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_merge_pairs<kW3>), dim3((unsigned)ph.tiles), dim3(kW3 * 64), lds, s, ph, b, ra, table, flip);
     return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@
 
 #include "mms_device.h"
 #include "mms_internal.h"
+#include "mms_tile_plan.h"
 
 namespace mms {
 
@@ -124,104 +125,8 @@ __device__ __forceinline__ void fetch_rows_async(const uint32_t* __restrict__ ta
                                          (__attribute__((address_space(3))) void*)rows, 4, 0, 0);
 }
 
-// Piece table of a tile, written by wave 0: start[k] (inside run k),
-// plen[k] (prefix of piece lengths), sbeg[k] (4-aligned LDS offsets).
-struct Meta {
-    uint32_t* start;
-    uint32_t* plen;
-    uint32_t* sbeg;
-    uint32_t* plan;   // [4 levels][16 waves][2]: each wave's work per level
-    uint32_t* cseg;   // piece whose LDS slots hold word 64*c (slot coordinates)
-};
-constexpr uint32_t kPlanWords = 4u * 16u * 2u;
+// words of one piece table (with its chunk table)
 constexpr uint32_t kMetaWords = 3u * 17u + kPlanWords + (kToutKeys + 4u * kMaxFanout) / 64u + 1u;
-
-// Exclusive sum over the 16 lanes of each row (DPP row shifts; a lane
-// shifted in from outside the row reads 0).
-__device__ __forceinline__ uint32_t excl_scan16(uint32_t x) {
-    uint32_t incl = x;
-    incl += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)incl, 0x111, 0xF, 0xF, false);   // row_shr:1
-    incl += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)incl, 0x112, 0xF, 0xF, false);   // row_shr:2
-    incl += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)incl, 0x114, 0xF, 0xF, false);   // row_shr:4
-    incl += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)incl, 0x118, 0xF, 0xF, false);   // row_shr:8
-    return incl - x;
-}
-
-// Work of every wave at every merge level of the tile, one (level, wave) per
-// lane (lane = 16 * level + wave).  Pair i of level l gets the waves whose
-// equal shares of the level's outputs have their midpoints inside it,
-// (2w+1) * total / (2W) in [plen[g0], plen[g2]), and they split it evenly at
-// multiples of 4; a pair holding no midpoint goes whole to the wave whose
-// share holds its start.  No quantity reaches 2^22 (udiv_small's range).
-template <int W>
-__device__ __forceinline__ void build_plan(const Meta& m, uint32_t Kg, int lane) {
-    const uint32_t total = m.plen[Kg];
-    const uint32_t l = (uint32_t)lane >> 4, w = (uint32_t)lane & 15u;
-    uint32_t nlev = 0;
-    while ((1u << nlev) < Kg) ++nlev;
-    const bool act = w < (uint32_t)W && l < nlev;
-    const uint32_t nseg = act ? (Kg + (1u << l) - 1u) >> l : 0u;
-    const uint32_t npairs = (nseg + 1u) >> 1;
-    const uint32_t mid2 = (2u * w + 1u) * total;           // 2W * midpoint
-    // output start of pair i of the level (i <= 8), read once
-    uint32_t pst[9];
-#pragma unroll
-    for (uint32_t i = 0; i < 9u; ++i) pst[i] = m.plen[min((2u * i) << l, Kg)];
-    uint32_t iw = 0;
-#pragma unroll
-    for (uint32_t i = 1; i < 8u; ++i)
-        if (i < npairs && 2u * (uint32_t)W * pst[i] <= mid2) iw = i;
-    const uint64_t grp = 0xFFFFull << (16u * (l & 3u));
-    uint32_t v0 = 0, nw = 1, own = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < 8u; ++i) {
-        const uint64_t mi = __ballot(act && i < npairs && iw == i) & grp;
-        if (act && i == iw && mi) {
-            v0 = (uint32_t)__builtin_ctzll(mi) - 16u * l;
-            nw = (uint32_t)__popcll(mi);
-        }
-        if (act && i < npairs && mi == 0ull && total) {
-            const uint32_t o = min(udiv_small(pst[i] * (uint32_t)W, total), (uint32_t)W - 1u);
-            if (o == w) own |= 1u << i;
-        }
-    }
-    if (act) {
-        uint32_t p0 = pst[0], p2 = pst[1];
-#pragma unroll
-        for (uint32_t i = 1; i < 8u; ++i)
-            if (iw == i) {
-                p0 = pst[i];
-                p2 = pst[i + 1u];
-            }
-        const uint32_t sz = p2 - p0, j = w - v0;
-        const uint32_t d0 = total ? udiv_small(sz * j, nw) & ~3u : 0u;
-        const uint32_t d1 = !total ? 0u : (j + 1u == nw ? sz : udiv_small(sz * (j + 1u), nw) & ~3u);
-        m.plan[2u * (uint32_t)lane] = iw | (d0 << 4) | (d1 << 18);
-        m.plan[2u * (uint32_t)lane + 1u] = own;
-    }
-}
-
-// Piece layout: start, plen and sbeg of every run and their totals.
-__device__ __forceinline__ void build_pieces(const Meta& m, uint32_t s, uint32_t e, const TileGeo& g, int lane) {
-    const bool own = (uint32_t)lane < g.Kg;
-    uint32_t len = own ? e - s : 0u;
-    uint32_t pl = excl_scan16(len);
-    // guards for memory safety only: keep the pieces inside the tile
-    len = pl >= g.cnt ? 0u : min(len, g.cnt - pl);
-    pl = min(pl, g.cnt);
-    const uint32_t sb = excl_scan16((len + 3u) & ~3u);
-    if (own) {
-        m.start[lane] = s;
-        m.plen[lane] = pl;
-        m.sbeg[lane] = sb;
-    }
-    const uint32_t tot_pl = (uint32_t)__builtin_amdgcn_readlane((int)(pl + len), (int)(g.Kg - 1u));
-    const uint32_t tot_sb = (uint32_t)__builtin_amdgcn_readlane((int)(sb + ((len + 3u) & ~3u)), (int)(g.Kg - 1u));
-    if (lane == 0) {
-        m.plen[g.Kg] = tot_pl;
-        m.sbeg[g.Kg] = tot_sb;
-    }
-}
 
 // Chunk table from the piece layout: largest k < Kg with sbeg[k] <= 64*c.
 __device__ __forceinline__ void build_chunks(const Meta& m, uint32_t Kg, int lane) {
@@ -240,7 +145,7 @@ __device__ __forceinline__ void build_chunks(const Meta& m, uint32_t Kg, int lan
 // The whole piece table by one wave (the pipeline's prologue).
 template <int W>
 __device__ __forceinline__ void build_meta(const Meta& m, uint32_t s, uint32_t e, const TileGeo& g, int lane) {
-    build_pieces(m, s, e, g, lane);
+    build_pieces(m, s, e, g.Kg, g.cnt, lane);
     lds_wave_sync();
     build_chunks(m, g.Kg, lane);
     build_plan<W>(m, g.Kg, lane);
@@ -361,7 +266,7 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
                 if (t + 2 * G < tiles) {
                     const TileGeo gp = tile_geo(ph, b, t + 2 * G, ra, lL);
                     load_split(table, t + 2 * G, gp, L, K, lane, s, e);
-                    build_pieces(meta(2), s, e, gp, lane);
+                    build_pieces(meta(2), s, e, gp.Kg, gp.cnt, lane);
                     if (t + 3 * G < tiles) fetch_rows_async(table, t + 3 * G, K, rows, lane);
                 }
             }
@@ -394,7 +299,7 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
             const TileGeo g3 = tile_geo(ph, b, t3, ra, lL);
             uint32_t s3, e3;
             split_from_rows(rows, g3, L, K, lane, s3, e3);
-            build_pieces(meta(nxt(nxt(nxt(cur)))), s3, e3, g3, lane);
+            build_pieces(meta(nxt(nxt(nxt(cur)))), s3, e3, g3.Kg, g3.cnt, lane);
             if (t3 + G < tiles) fetch_rows_async(table, t3 + G, K, rows, lane);
         }
         // waves 1 and 2: chunk table and wave plan of tile t+2G

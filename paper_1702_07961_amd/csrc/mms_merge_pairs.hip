@@ -1,0 +1,177 @@
+// Key-value K-way merge round (§4.2, values moving with their keys), one
+// workgroup per output tile.
+//
+// A tile's input is the K pieces of its group's runs bounded by the split
+// indices of its first and last output (§4.1).  Wave 0 lays the pieces out at
+// 4-aligned LDS slots and plans every merge level's work per wave; the
+// pieces' keys and values then go into LDS through the memory unit.  The
+// merge tree runs on (key, tag) pairs packed into 64-bit words (tag = the
+// pair's slot as loaded, which orders equal keys stably): level 0 reads the
+// loaded keys, later levels read keys and 16-bit tags written by the level
+// before, and the last level stores keys to memory with each value gathered
+// from its slot.  LDS (words, cap = Tout + 4K slots): keys 2 x cap, tags
+// 2 x cap/2, values cap, the waves' transpose scratch, the piece table and
+// plan; for Tout = 3840 two workgroups share a compute unit.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mms_device.h"
+#include "mms_device_kt.h"
+#include "mms_internal.h"
+#include "mms_tile_plan.h"
+
+namespace mms {
+
+namespace {
+
+constexpr int kEMP = 8;   // 64 x 8-pair merge blocks
+constexpr uint32_t kMetaWordsP = 3u * 17u + kPlanWords;
+
+// One planned merge level (the plan's encoding as in the keys merge).
+template <class Src, class Sink>
+__device__ __forceinline__ void merge_level_kt(const Src& X, const Meta& mt, uint32_t nseg0, uint32_t lvl,
+                                               const Sink& out, uint32_t* scr, int wave, int lane) {
+    const uint32_t* pw = mt.plan + 2u * (lvl * 16u + (uint32_t)wave);
+    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)pw[0]);
+    uint32_t own = (uint32_t)__builtin_amdgcn_readfirstlane((int)pw[1]);
+    auto run = [&](uint32_t i, uint32_t d0, uint32_t d1, bool whole) {
+        const uint32_t g0 = min((2u * i) << lvl, nseg0);
+        const uint32_t g1 = min((2u * i + 1u) << lvl, nseg0);
+        const uint32_t g2 = min((2u * i + 2u) << lvl, nseg0);
+        const uint32_t aA = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.sbeg[g0]);
+        const uint32_t aB = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.sbeg[g1]);
+        const uint32_t p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.plen[g0]);
+        const uint32_t p1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.plen[g1]);
+        const uint32_t p2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.plen[g2]);
+        const uint32_t la = p1 - p0, lb = p2 - p1;
+        if (whole) d1 = la + lb;
+        if (d0 < d1) merge_pair_range_kt<kEMP>(X, aA, la, aB, lb, d0, d1, out, aA, scr, lane);
+    };
+    run(w0 & 15u, (w0 >> 4) & 0x3FFFu, w0 >> 18, false);
+    while (own) {
+        const uint32_t i = (uint32_t)__builtin_ctz(own);
+        own &= own - 1u;
+        run(i, 0u, 0u, true);
+    }
+}
+
+}  // namespace
+
+template <int W>
+__global__ __launch_bounds__(W * 64, 4) void k_merge_pairs(Phase ph, Bufs b, RoundArgs ra,
+                                                           const uint32_t* __restrict__ table, uint32_t flip) {
+    const uint32_t Tout = ra.Tout, K = ra.K;
+    const uint64_t L = ra.L;
+    const uint32_t cap = Tout + 4u * K;
+    extern __shared__ __align__(16) uint32_t smem[];
+    uint32_t* K0 = smem;
+    uint32_t* K1 = K0 + cap;
+    uint16_t* T0 = reinterpret_cast<uint16_t*>(K1 + cap);
+    uint16_t* T1 = T0 + cap;
+    uint32_t* V = reinterpret_cast<uint32_t*>(T1 + cap);
+    uint32_t* scr = V + cap;
+    uint32_t* mb = scr + W * Xpose<kEMP>::WORDS;
+    const Meta mt{mb, mb + 17, mb + 34, mb + 51, nullptr};
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
+    uint32_t* wscr = scr + (uint32_t)wave * Xpose<kEMP>::WORDS;
+    const uint64_t t = blockIdx.x;
+    const TileRef tr = tile_ref(ph, b, t);
+    const uint32_t flip_out = tr.final_pass ? flip : 0u;
+    const uint32_t grp = tr.local / (uint32_t)ra.tpg;
+    const uint64_t i = tr.local - (uint64_t)grp * ra.tpg;
+    const uint64_t span = (uint64_t)K * L;
+    const uint64_t gb = (uint64_t)grp * span;
+    const uint64_t glen = min(span, tr.n - gb);
+    const uint32_t Kg = (uint32_t)((glen + L - 1) / L);
+    const uint64_t obeg = i * (uint64_t)Tout;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(Tout, glen - obeg);
+    const uint64_t obase = gb + obeg;
+
+    if (Kg == 1) {   // a lone run: its tile is already in order
+        for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
+            gptr(tr.dst_k)[obase + j] = gptr(tr.src_k)[obase + j] ^ flip_out;
+            gptr(tr.dst_v)[obase + j] = gptr(tr.src_v)[obase + j];
+        }
+        return;
+    }
+    if (wave == 0) {   // lane k < Kg: the split indices of run k, then the layout and plan
+        uint32_t s = 0, e = 0;
+        if ((uint32_t)lane < Kg) {
+            const uint32_t k = (uint32_t)lane;
+            const uint32_t nk = (uint32_t)min(L, glen - (uint64_t)k * L);
+            // the clamps only guard memory safety; exact splits never trigger them
+            s = i == 0 ? 0u : min(table[t * K + k], nk);
+            e = (obeg + Tout >= glen) ? nk : min(max(table[(t + 1) * K + k], s), nk);
+        }
+        build_pieces(mt, s, e, Kg, cnt, lane);
+        lds_wave_sync();
+        build_plan<W>(mt, Kg, lane);
+    }
+    lds_barrier();
+    // The pieces' keys and values go into LDS by the memory unit, 64 words
+    // per instruction; chunks are dealt to the waves round-robin in piece
+    // order.
+    {
+        uint32_t cbase = 0;   // chunks of the earlier pieces
+        for (uint32_t k = 0; k < Kg; ++k) {
+            const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.sbeg[k]);
+            const uint32_t len = (uint32_t)__builtin_amdgcn_readfirstlane((int)(mt.plen[k + 1] - mt.plen[k]));
+            const uint32_t st = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.start[k]);
+            const uint32_t nch = (len + 63u) >> 6;
+            const uint64_t run0 = gb + (uint64_t)k * L + st;   // the piece's first element
+            for (uint32_t c = ((uint32_t)wave + W - cbase % W) % W; c < nch; c += W) {
+                if (64u * c + (uint32_t)lane < len) {
+                    dma_dword(tr.src_k + run0 + 64u * c, (uint32_t)lane, K0 + s0 + 64u * c);
+                    dma_dword(tr.src_v + run0 + 64u * c, (uint32_t)lane, V + s0 + 64u * c);
+                }
+            }
+            cbase += nch;
+        }
+        vm_drain();
+    }
+    lds_barrier();
+
+    uint32_t nlev = 0;
+    while ((1u << nlev) < Kg) ++nlev;
+    uint32_t* Xk = K0;
+    uint16_t* Xt = T0;
+    uint32_t* Yk = K1;
+    uint16_t* Yt = T1;
+    const bool vec = (((uintptr_t)(tr.dst_k + obase) | (uintptr_t)(tr.dst_v + obase)) & 15u) == 0;
+    for (uint32_t lvl = 0; lvl < nlev; ++lvl) {
+        const bool last = lvl + 1u == nlev;
+        if (lvl == 0) {
+            const KtSrcLoaded X{Xk};
+            if (last) merge_level_kt(X, mt, Kg, lvl, KtSinkGlobal{tr.dst_k + obase, tr.dst_v + obase, V, flip_out, cnt, vec}, wscr, wave, lane);
+            else merge_level_kt(X, mt, Kg, lvl, KtSinkLds{Yk, Yt}, wscr, wave, lane);
+        } else {
+            const KtSrcTagged X{Xk, Xt};
+            if (last) merge_level_kt(X, mt, Kg, lvl, KtSinkGlobal{tr.dst_k + obase, tr.dst_v + obase, V, flip_out, cnt, vec}, wscr, wave, lane);
+            else merge_level_kt(X, mt, Kg, lvl, KtSinkLds{Yk, Yt}, wscr, wave, lane);
+        }
+        lds_barrier();
+        uint32_t* tk = Xk; Xk = Yk; Yk = tk;
+        uint16_t* tt = Xt; Xt = Yt; Yt = tt;
+    }
+}
+
+static hipError_t allow_lds(const void* f, size_t bytes) {
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_merge_pairs(const Phase& ph, const Bufs& b, const RoundArgs& ra, const uint32_t* table,
+                              uint32_t flip, hipStream_t s) {
+    if (ph.tiles == 0) return hipSuccess;
+    // tags are 16-bit slots; the plan encodes outputs in 14 bits
+    if (ra.Tout > kToutPairs || ra.Tout % 4 || ra.K > kMaxFanout) return hipErrorInvalidValue;
+    const uint32_t cap = ra.Tout + 4u * ra.K;
+    const size_t lds = (4u * cap + kW3 * Xpose<kEMP>::WORDS + kMetaWordsP) * sizeof(uint32_t);
+    hipError_t e = allow_lds((const void*)k_merge_pairs<kW3>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_merge_pairs<kW3>), dim3((unsigned)ph.tiles), dim3(kW3 * 64), lds, s, ph, b, ra, table, flip);
+    return hipGetLastError();
+}
+
+}  // namespace mms

@@ -40,7 +40,7 @@ def test_committed_tuning_table_loads():
         assert lib.mms_get_tuning(1 << e["max_log2_n"], _lib.MMS_PAIRS, t) == 0
         assert (t.fanout, t.base, t.flags) == (e["fanout"], e["base"], _lib.MMS_PAIRS)
     # pairs keep the key-value merge tile whatever the table says
-    assert lib.mms_get_tuning(1 << 27, _lib.MMS_PAIRS, t) == 0 and t.merge_tile == 4096
+    assert lib.mms_get_tuning(1 << 27, _lib.MMS_PAIRS, t) == 0 and t.merge_tile == 3840
 
 
 def test_autotune_candidates():
