@@ -8,12 +8,9 @@
 // data-dependent shared-memory addressing is what costs the pairwise
 // mergesorts their bank conflicts).
 //
-// Element kinds:
-//   Elem<false>  a 32-bit key (unsigned order; signed keys are mapped with
-//                key ^ 0x80000000 on the way in and back on the way out)
-//   Elem<true>   key, tag, value.  The tag is the element's position in the
-//                array the current pass reads, so (key, tag) order is the
-//                stable order and every network sorts stably.
+// Element kinds: Elem<false> is a 32-bit key (unsigned order; signed keys
+// are mapped with key ^ 0x80000000 on the way in and back on the way out).
+// Key-value sorts use the (key, tag) words of mms_device_kt.h.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -37,36 +34,21 @@ typedef __attribute__((address_space(1))) u32x4 gu32x4;
 
 __device__ __forceinline__ gu32* gptr(uint32_t* p) { return (gu32*)p; }
 __device__ __forceinline__ cgu32* gptr(const uint32_t* p) { return (cgu32*)p; }
-constexpr uint32_t kSentTag = 0xFFFFFFFFu;
 
 template <bool P> struct Elem;
 template <> struct Elem<false> {
     uint32_t k;
     __device__ static Elem sentinel() { return {kSentKey}; }
 };
-template <> struct Elem<true> {
-    uint32_t k, t, v;
-    __device__ static Elem sentinel() { return {kSentKey, kSentTag, 0u}; }
-};
 
 // strict "a comes before b"
 __device__ __forceinline__ bool before(const Elem<false>& a, const Elem<false>& b) { return a.k < b.k; }
-__device__ __forceinline__ bool before(const Elem<true>& a, const Elem<true>& b) {
-    uint64_t x = ((uint64_t)a.k << 32) | a.t, y = ((uint64_t)b.k << 32) | b.t;
-    return x < y;
-}
 
 // compare-exchange: lo receives the earlier element, hi the later one
 __device__ __forceinline__ void cex(Elem<false>& lo, Elem<false>& hi) {
     uint32_t a = lo.k, b = hi.k;
     lo.k = min(a, b);
     hi.k = max(a, b);
-}
-__device__ __forceinline__ void cex(Elem<true>& lo, Elem<true>& hi) {
-    bool sw = before(hi, lo);
-    Elem<true> a = lo, b = hi;
-    lo.k = sw ? b.k : a.k; lo.t = sw ? b.t : a.t; lo.v = sw ? b.v : a.v;
-    hi.k = sw ? a.k : b.k; hi.t = sw ? a.t : b.t; hi.v = sw ? a.v : b.v;
 }
 
 // Median of three unsigned values in one instruction: with c = 0 it is
@@ -81,15 +63,6 @@ __device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c)
 // keep the earlier (want_first) or the later of `mine` and `other`
 __device__ __forceinline__ Elem<false> pick(const Elem<false>& mine, const Elem<false>& other, bool want_first) {
     return {med3_u32(mine.k, other.k, want_first ? 0u : ~0u)};
-}
-__device__ __forceinline__ Elem<true> pick(const Elem<true>& mine, const Elem<true>& other, bool want_first) {
-    bool other_first = before(other, mine);
-    bool take = want_first ? other_first : !other_first;
-    Elem<true> r;
-    r.k = take ? other.k : mine.k;
-    r.t = take ? other.t : mine.t;
-    r.v = take ? other.v : mine.v;
-    return r;
 }
 
 // Value of lane (lane ^ m).  When m is a constant (after loop unrolling)
@@ -116,9 +89,6 @@ __device__ __forceinline__ uint32_t shfl_xor_u32(uint32_t x, int m) {
     }
 }
 __device__ __forceinline__ Elem<false> shfl_xor(const Elem<false>& e, int m) { return {shfl_xor_u32(e.k, m)}; }
-__device__ __forceinline__ Elem<true> shfl_xor(const Elem<true>& e, int m) {
-    return {shfl_xor_u32(e.k, m), shfl_xor_u32(e.t, m), shfl_xor_u32(e.v, m)};
-}
 
 // ---------------------------------------------------------------------------
 // Base case: sort the 64*E elements a wave holds, E per lane (§4.3 sorts a
@@ -204,21 +174,6 @@ __device__ __forceinline__ void bitonic_merge_striped(El (&m)[EM], int lane) {
     }
 }
 
-// LDS views of a merge buffer: key(i) is the key at LDS position i, get(i)
-// the whole element, whose tag is its LDS position (the pass's stable
-// order), put(i, e) stores an element (a view is also a merge-level sink).
-struct LdsKV32 {
-    using El = Elem<true>;
-    uint32_t* k;
-    uint32_t* v;
-    __device__ __forceinline__ uint32_t key(uint32_t i) const { return k[i]; }
-    __device__ __forceinline__ El get(uint32_t i) const { return {k[i], i, v[i]}; }
-    __device__ __forceinline__ void put(uint32_t i, const El& e) const {
-        k[i] = e.k;
-        v[i] = e.v;
-    }
-};
-
 // ---------------------------------------------------------------------------
 // Merge-path split inside LDS: the number p of elements of A = X[aA, aA+la)
 // among the first d elements of merge(A, B = X[aB, aB+lb)), A first on ties.
@@ -279,21 +234,6 @@ __device__ __forceinline__ uint32_t lds_corank2_view(const View& X, uint32_t aA,
     }
     return lo;
 }
-// Writes to memory, undoing the signed-key mapping; positions >= lim are
-// dropped (they hold the sentinels of a ragged tile).
-template <bool P> struct GlobalSinkLim {
-    uint32_t* k;
-    uint32_t* v;
-    uint32_t flip;
-    uint32_t lim;
-    __device__ __forceinline__ void put(uint32_t i, const Elem<P>& e) const {
-        if (i < lim) {
-            gptr(k)[i] = e.k ^ flip;
-            if constexpr (P) gptr(v)[i] = e.v;
-        }
-    }
-};
-
 // ---------------------------------------------------------------------------
 // Merge outputs [d0, d1) of the pair (A, B) in blocks of N = 64*EM.  Each
 // block reads the next N candidates of A (ascending) and of B (descending),

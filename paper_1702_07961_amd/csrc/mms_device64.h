@@ -20,6 +20,7 @@
 namespace mms {
 
 constexpr uint64_t kSentKey64 = ~0ull;
+constexpr uint32_t kSentTag = 0xFFFFFFFFu;   // above every tag
 constexpr uint64_t kSignFlip64 = 0x8000000000000000ull;
 
 typedef __attribute__((address_space(1))) uint64_t gu64;

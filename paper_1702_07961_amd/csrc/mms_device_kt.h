@@ -139,8 +139,7 @@ __device__ __forceinline__ void block_sort_kt(double (&m)[EM], uint32_t* scr, in
 #pragma unroll
     for (int e = 0; e < EM; ++e) {
         const double a = kt_join(hi[e], lo[e]), o = kt_join(oh[e], ol[e]);
-        const double mn = kt_min(a, o), mx = kt_max(a, o);
-        m[e] = keep_max ? mx : mn;
+        m[e] = ((o < a) != keep_max) ? o : a;   // one compare, two selects
     }
 #pragma unroll
     for (int c = 0; c < EM / 4; ++c) {                   // index bits 1..0
@@ -149,6 +148,22 @@ __device__ __forceinline__ void block_sort_kt(double (&m)[EM], uint32_t* scr, in
         cex_kt(m[4 * c + 0], m[4 * c + 1]);
         cex_kt(m[4 * c + 2], m[4 * c + 3]);
     }
+}
+
+// A (key, tag) word as an element of the generic networks (wave_sort_blocked,
+// wave_merge_tail): compare-exchange by min and max, a lane-dependent pick by
+// one compare, and lane exchanges of both halves.
+struct ElemKT {
+    double d;
+    __device__ static ElemKT sentinel() { return {kt_sentinel()}; }
+};
+__device__ __forceinline__ void cex(ElemKT& lo, ElemKT& hi) { cex_kt(lo.d, hi.d); }
+__device__ __forceinline__ ElemKT pick(const ElemKT& mine, const ElemKT& other, bool want_first) {
+    const bool other_first = other.d < mine.d;
+    return (want_first == other_first) ? other : mine;
+}
+__device__ __forceinline__ ElemKT shfl_xor(const ElemKT& e, int m) {
+    return {kt_join(shfl_xor_u32(kt_hi(e.d), m), shfl_xor_u32(kt_lo(e.d), m))};
 }
 
 // Number of block positions k with a_k < b_k (a increasing and b
@@ -167,9 +182,21 @@ __device__ __forceinline__ uint32_t prefix_len_kt(const double (&a)[EM], const d
 
 // LDS sources of a merge level.  Level 0 reads the keys as loaded, each
 // element's tag being its own slot; later levels read keys and 16-bit tags.
+// from(i) gives a cursor at slot i whose at(off) reads slot i + off, so the
+// reads of a block share one address register and constant offsets; raw
+// returns the key and tag unpacked, so a block's reads can all be issued
+// before the first is used.
 struct KtSrcLoaded {
     const uint32_t* k;
-    __device__ __forceinline__ double at(uint32_t i) const { return kt_pack(k[i], i); }
+    struct Cur {
+        const uint32_t* k;
+        uint32_t t0;
+        __device__ __forceinline__ void raw(uint32_t off, uint32_t& key, uint32_t& tag) const {
+            key = k[off];
+            tag = t0 + off;
+        }
+    };
+    __device__ __forceinline__ Cur from(uint32_t i) const { return {k + i, i}; }
     // pairs i .. i+3 (i a multiple of 4)
     __device__ __forceinline__ void at4(uint32_t i, double* r) const {
         const uint4 v = *reinterpret_cast<const uint4*>(k + i);
@@ -182,7 +209,15 @@ struct KtSrcLoaded {
 struct KtSrcTagged {
     const uint32_t* k;
     const uint16_t* t;
-    __device__ __forceinline__ double at(uint32_t i) const { return kt_pack(k[i], t[i]); }
+    struct Cur {
+        const uint32_t* k;
+        const uint16_t* t;
+        __device__ __forceinline__ void raw(uint32_t off, uint32_t& key, uint32_t& tag) const {
+            key = k[off];
+            tag = t[off];
+        }
+    };
+    __device__ __forceinline__ Cur from(uint32_t i) const { return {k + i, t + i}; }
     __device__ __forceinline__ void at4(uint32_t i, double* r) const {
         const uint4 v = *reinterpret_cast<const uint4*>(k + i);
         const uint2 w = *reinterpret_cast<const uint2*>(t + i);
@@ -258,6 +293,23 @@ struct KtSinkGlobal {
     }
 };
 
+// A block's candidates: a_e = A[64e] (lane's own offset in A) and b_e =
+// B[64(EM-1-e)], every read issued before any is packed.
+template <int EM, class Cur>
+__device__ __forceinline__ void read_block(const Cur& A, const Cur& B, double (&a)[EM], double (&b)[EM]) {
+    uint32_t ka[EM], ta[EM], kb[EM], tb[EM];
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+        A.raw((uint32_t)e * kWave, ka[e], ta[e]);
+        B.raw((uint32_t)(EM - 1 - e) * kWave, kb[e], tb[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+        a[e] = kt_pack(ka[e], ta[e]);
+        b[e] = kt_pack(kb[e], tb[e]);
+    }
+}
+
 // Merge outputs [d0, d1) of A = X[aA, aA+la) and B = X[aB, aB+lb) in blocks
 // of N = 64*EM pairs, the key-value form of merge_pair_range_keys: A holds
 // the smaller tags, so the split on keys with A first on ties is the split
@@ -286,14 +338,12 @@ __device__ __forceinline__ void merge_pair_range_kt(const Src& X, uint32_t aA, u
         double m[EM];
         uint32_t u;
         if (p + N <= la && q + N <= lb) {
-            const uint32_t ia = aA + p + (uint32_t)lane;
-            const uint32_t ib = aB + q + (N - 1u) - (uint32_t)lane;
+            // b's reads from its lowest position up, so every address is a
+            // base plus a constant offset
+            const auto A = X.from(aA + p + (uint32_t)lane);
+            const auto B = X.from(aB + q + (N - 1u) - (uint32_t)lane - (uint32_t)(EM - 1) * kWave);
             double a[EM], b[EM];
-#pragma unroll
-            for (int e = 0; e < EM; ++e) {
-                a[e] = X.at(ia + (uint32_t)e * kWave);
-                b[e] = X.at(ib - (uint32_t)e * kWave);
-            }
+            read_block<EM>(A, B, a, b);
 #pragma unroll
             for (int e = 0; e < EM; ++e) m[e] = kt_min(a[e], b[e]);
             u = prefix_len_kt<0, EM, EM>(a, b);
@@ -304,15 +354,11 @@ __device__ __forceinline__ void merge_pair_range_kt(const Src& X, uint32_t aA, u
             // return is discarded.  The sentinel is above every pair, so
             // the cursors only pass a run's end in the tile's last block.
             const uint32_t pc = min(p, la), qc = min(q, lb);
-            const uint32_t ia = aA + pc + (uint32_t)lane;
-            const uint32_t ib = aB + qc + (N - 1u) - (uint32_t)lane;
+            const auto A = X.from(aA + pc + (uint32_t)lane);
+            const auto B = X.from(aB + qc + (N - 1u) - (uint32_t)lane - (uint32_t)(EM - 1) * kWave);
             const uint32_t ra = la - pc, rb = lb - qc;
             double a[EM], b[EM];
-#pragma unroll
-            for (int e = 0; e < EM; ++e) {
-                a[e] = X.at(ia + (uint32_t)e * kWave);
-                b[e] = X.at(ib - (uint32_t)e * kWave);
-            }
+            read_block<EM>(A, B, a, b);
 #pragma unroll
             for (int e = 0; e < EM; ++e) {
                 const uint32_t k = (uint32_t)e * kWave + (uint32_t)lane;

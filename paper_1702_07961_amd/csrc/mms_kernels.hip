@@ -14,6 +14,7 @@
 
 #include "mms_corank.h"
 #include "mms_device.h"
+#include "mms_device_kt.h"
 #include "mms_internal.h"
 
 namespace mms {
@@ -128,10 +129,11 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort_keys(Phase ph, Bufs b, uin
 }
 
 // ===========================================================================
-// Key-value base case, same scheme as the keys-only one.  Elements carry
-// (key, tag) with tag = tile position, so (key, tag) is the stable order and
-// is unique; the values are staged in LDS as loaded and gathered by tag when
-// the sorted tile is stored.  Exchanges move keys and tags as two arrays.
+// Key-value base case, same scheme as the keys-only one.  Elements are
+// (key, tag) words (mms_device_kt.h) with tag = tile position, so their order
+// is the stable order and is unique; the values are staged in LDS as loaded
+// and gathered by tag when the sorted tile is stored.  Exchanges move the
+// words' high and low halves as two arrays in the conflict-free chunk layout.
 // LDS: values (T words), then two exchange buffers of 2T words.
 // ===========================================================================
 template <int E, int W>
@@ -155,51 +157,53 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort_pairs(Phase ph, Bufs b, ui
     uint32_t* out_v = tr.dst_v + base;
     const uint32_t flip_out = tr.final_pass ? flip : 0u;
 
-    Elem<true> r[E];
+    ElemKT r[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t j = (uint32_t)wave * CH + (uint32_t)e * 64u + ul;
         if (j < cnt) {
-            r[e] = Elem<true>{gptr(in_k)[j] ^ flip, j, 0u};
+            r[e] = ElemKT{kt_pack(gptr(in_k)[j] ^ flip, j)};
             V[j] = gptr(in_v)[j];
         } else {
-            r[e] = Elem<true>::sentinel();
+            r[e] = ElemKT::sentinel();
         }
     }
     wave_sort_blocked<E>(r, lane);
 
     uint32_t buf = 0;
     auto exchange = [&](int pw, bool mirror, bool want_first) {
-        uint32_t* Xk = smem + T + buf * 2u * T;
-        uint32_t* Xt = Xk + T;
+        uint32_t* Xh = smem + T + buf * 2u * T;
+        uint32_t* Xl = Xh + T;
         buf ^= 1u;
         const uint32_t me = (uint32_t)wave * CH;
 #pragma unroll
         for (uint32_t c = 0; c < Q; ++c) {
             const uint32_t w = me + chunk_word<E>(ul, c);
-            *reinterpret_cast<uint4*>(Xk + w) = make_uint4(r[4 * c].k, r[4 * c + 1].k, r[4 * c + 2].k, r[4 * c + 3].k);
-            *reinterpret_cast<uint4*>(Xt + w) = make_uint4(r[4 * c].t, r[4 * c + 1].t, r[4 * c + 2].t, r[4 * c + 3].t);
+            *reinterpret_cast<uint4*>(Xh + w) = make_uint4(kt_hi(r[4 * c].d), kt_hi(r[4 * c + 1].d),
+                                                           kt_hi(r[4 * c + 2].d), kt_hi(r[4 * c + 3].d));
+            *reinterpret_cast<uint4*>(Xl + w) = make_uint4(kt_lo(r[4 * c].d), kt_lo(r[4 * c + 1].d),
+                                                           kt_lo(r[4 * c + 2].d), kt_lo(r[4 * c + 3].d));
         }
         lds_barrier();
         const uint32_t them = (uint32_t)pw * CH;
 #pragma unroll
         for (uint32_t c = 0; c < Q; ++c) {
-            uint32_t ok[4], ot[4];
+            uint32_t oh[4], ol[4];
             if (mirror) {
                 const uint32_t w = them + chunk_word<E>(63u - ul, Q - 1u - c);
-                const uint4 vk = *reinterpret_cast<const uint4*>(Xk + w);
-                const uint4 vt = *reinterpret_cast<const uint4*>(Xt + w);
-                ok[0] = vk.w; ok[1] = vk.z; ok[2] = vk.y; ok[3] = vk.x;
-                ot[0] = vt.w; ot[1] = vt.z; ot[2] = vt.y; ot[3] = vt.x;
+                const uint4 vh = *reinterpret_cast<const uint4*>(Xh + w);
+                const uint4 vl = *reinterpret_cast<const uint4*>(Xl + w);
+                oh[0] = vh.w; oh[1] = vh.z; oh[2] = vh.y; oh[3] = vh.x;
+                ol[0] = vl.w; ol[1] = vl.z; ol[2] = vl.y; ol[3] = vl.x;
             } else {
                 const uint32_t w = them + chunk_word<E>(ul, c);
-                const uint4 vk = *reinterpret_cast<const uint4*>(Xk + w);
-                const uint4 vt = *reinterpret_cast<const uint4*>(Xt + w);
-                ok[0] = vk.x; ok[1] = vk.y; ok[2] = vk.z; ok[3] = vk.w;
-                ot[0] = vt.x; ot[1] = vt.y; ot[2] = vt.z; ot[3] = vt.w;
+                const uint4 vh = *reinterpret_cast<const uint4*>(Xh + w);
+                const uint4 vl = *reinterpret_cast<const uint4*>(Xl + w);
+                oh[0] = vh.x; oh[1] = vh.y; oh[2] = vh.z; oh[3] = vh.w;
+                ol[0] = vl.x; ol[1] = vl.y; ol[2] = vl.z; ol[3] = vl.w;
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) r[4 * c + j] = pick(r[4 * c + j], Elem<true>{ok[j], ot[j], 0u}, want_first);
+            for (int j = 0; j < 4; ++j) r[4 * c + j] = pick(r[4 * c + j], ElemKT{kt_join(oh[j], ol[j])}, want_first);
         }
     };
 #pragma unroll
@@ -218,17 +222,18 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort_pairs(Phase ph, Bufs b, ui
 #pragma unroll
     for (uint32_t c = 0; c < Q; ++c) {
         const uint32_t pos = (uint32_t)wave * CH + ul * (uint32_t)E + 4u * c;
+        const ElemKT* q = r + 4 * c;
         if (vec && pos + 4u <= cnt) {
-            *reinterpret_cast<gu32x4*>(gk + pos) = u32x4{r[4 * c].k ^ flip_out, r[4 * c + 1].k ^ flip_out,
-                                                         r[4 * c + 2].k ^ flip_out, r[4 * c + 3].k ^ flip_out};
+            *reinterpret_cast<gu32x4*>(gk + pos) = u32x4{kt_key(q[0].d) ^ flip_out, kt_key(q[1].d) ^ flip_out,
+                                                         kt_key(q[2].d) ^ flip_out, kt_key(q[3].d) ^ flip_out};
             *reinterpret_cast<gu32x4*>(gv + pos) =
-                u32x4{V[r[4 * c].t], V[r[4 * c + 1].t], V[r[4 * c + 2].t], V[r[4 * c + 3].t]};
+                u32x4{V[kt_tag(q[0].d)], V[kt_tag(q[1].d)], V[kt_tag(q[2].d)], V[kt_tag(q[3].d)]};
         } else {
 #pragma unroll
             for (uint32_t j = 0; j < 4; ++j) {
                 if (pos + j < cnt) {
-                    gk[pos + j] = r[4 * c + j].k ^ flip_out;
-                    gv[pos + j] = V[r[4 * c + j].t];
+                    gk[pos + j] = kt_key(q[j].d) ^ flip_out;
+                    gv[pos + j] = V[kt_tag(q[j].d)];
                 }
             }
         }

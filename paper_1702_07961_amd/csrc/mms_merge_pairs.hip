@@ -96,29 +96,28 @@ __global__ __launch_bounds__(W * 64, 4) void k_merge_pairs(Phase ph, Bufs b, Rou
         }
         return;
     }
-    if (wave == 0) {   // lane k < Kg: the split indices of run k, then the layout and plan
-        uint32_t s = 0, e = 0;
-        if ((uint32_t)lane < Kg) {
-            const uint32_t k = (uint32_t)lane;
-            const uint32_t nk = (uint32_t)min(L, glen - (uint64_t)k * L);
-            // the clamps only guard memory safety; exact splits never trigger them
-            s = i == 0 ? 0u : min(table[t * K + k], nk);
-            e = (obeg + Tout >= glen) ? nk : min(max(table[(t + 1) * K + k], s), nk);
-        }
-        build_pieces(mt, s, e, Kg, cnt, lane);
-        lds_wave_sync();
-        build_plan<W>(mt, Kg, lane);
+    // Every wave reads the tile's split indices (lane k < Kg: run k) and
+    // lays the pieces out in registers, so its loads into LDS go out at
+    // once; wave 0 also writes the layout and plans the merge levels while
+    // they are in flight.
+    uint32_t s = 0, e = 0;
+    if ((uint32_t)lane < Kg) {
+        const uint32_t k = (uint32_t)lane;
+        const uint32_t nk = (uint32_t)min(L, glen - (uint64_t)k * L);
+        // the clamps only guard memory safety; exact splits never trigger them
+        s = i == 0 ? 0u : min(table[t * K + k], nk);
+        e = (obeg + Tout >= glen) ? nk : min(max(table[(t + 1) * K + k], s), nk);
     }
-    lds_barrier();
-    // The pieces' keys and values go into LDS by the memory unit, 64 words
-    // per instruction; chunks are dealt to the waves round-robin in piece
-    // order.
     {
+        // The pieces' keys and values go into LDS by the memory unit, 64
+        // words per instruction; chunks are dealt to the waves round-robin in
+        // piece order.
+        const PieceLayout pc = piece_layout(s, e, Kg, cnt, lane);
         uint32_t cbase = 0;   // chunks of the earlier pieces
         for (uint32_t k = 0; k < Kg; ++k) {
-            const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.sbeg[k]);
-            const uint32_t len = (uint32_t)__builtin_amdgcn_readfirstlane((int)(mt.plen[k + 1] - mt.plen[k]));
-            const uint32_t st = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.start[k]);
+            const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)pc.sb, (int)k);
+            const uint32_t len = (uint32_t)__builtin_amdgcn_readlane((int)pc.len, (int)k);
+            const uint32_t st = (uint32_t)__builtin_amdgcn_readlane((int)s, (int)k);
             const uint32_t nch = (len + 63u) >> 6;
             const uint64_t run0 = gb + (uint64_t)k * L + st;   // the piece's first element
             for (uint32_t c = ((uint32_t)wave + W - cbase % W) % W; c < nch; c += W) {
@@ -129,8 +128,13 @@ __global__ __launch_bounds__(W * 64, 4) void k_merge_pairs(Phase ph, Bufs b, Rou
             }
             cbase += nch;
         }
-        vm_drain();
     }
+    if (wave == 0) {
+        build_pieces(mt, s, e, Kg, cnt, lane);
+        lds_wave_sync();
+        build_plan<W>(mt, Kg, lane);
+    }
+    vm_drain();
     lds_barrier();
 
     uint32_t nlev = 0;

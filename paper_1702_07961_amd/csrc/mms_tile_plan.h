@@ -86,11 +86,13 @@ __device__ __forceinline__ void build_plan(const Meta& m, uint32_t Kg, int lane)
     }
 }
 
-// Piece layout of a tile of cnt outputs from Kg runs (lane k < Kg holds
-// run k's split indices s <= e): start, plen and sbeg of every run and their
-// totals.
-__device__ __forceinline__ void build_pieces(const Meta& m, uint32_t s, uint32_t e, uint32_t Kg, uint32_t cnt,
-                                             int lane) {
+// Piece layout of a tile of cnt outputs from Kg runs, in registers: lane
+// k < Kg, holding run k's split indices s <= e, gets its piece's length, its
+// first output (plen) and its 4-aligned first LDS slot (sbeg).
+struct PieceLayout {
+    uint32_t len, pl, sb;
+};
+__device__ __forceinline__ PieceLayout piece_layout(uint32_t s, uint32_t e, uint32_t Kg, uint32_t cnt, int lane) {
     const bool own = (uint32_t)lane < Kg;
     uint32_t len = own ? e - s : 0u;
     uint32_t pl = excl_scan16(len);
@@ -98,18 +100,26 @@ __device__ __forceinline__ void build_pieces(const Meta& m, uint32_t s, uint32_t
     len = pl >= cnt ? 0u : min(len, cnt - pl);
     pl = min(pl, cnt);
     const uint32_t sb = excl_scan16((len + 3u) & ~3u);
-    if (own) {
+    return {len, pl, sb};
+}
+
+// The piece layout written to the tile's table: start, plen and sbeg of
+// every run and their totals.
+__device__ __forceinline__ void build_pieces(const Meta& m, uint32_t s, uint32_t e, uint32_t Kg, uint32_t cnt,
+                                             int lane) {
+    const PieceLayout pc = piece_layout(s, e, Kg, cnt, lane);
+    if ((uint32_t)lane < Kg) {
         m.start[lane] = s;
-        m.plen[lane] = pl;
-        m.sbeg[lane] = sb;
+        m.plen[lane] = pc.pl;
+        m.sbeg[lane] = pc.sb;
     }
-    const uint32_t tot_pl = (uint32_t)__builtin_amdgcn_readlane((int)(pl + len), (int)(Kg - 1u));
-    const uint32_t tot_sb = (uint32_t)__builtin_amdgcn_readlane((int)(sb + ((len + 3u) & ~3u)), (int)(Kg - 1u));
+    const uint32_t tot_pl = (uint32_t)__builtin_amdgcn_readlane((int)(pc.pl + pc.len), (int)(Kg - 1u));
+    const uint32_t tot_sb =
+        (uint32_t)__builtin_amdgcn_readlane((int)(pc.sb + ((pc.len + 3u) & ~3u)), (int)(Kg - 1u));
     if (lane == 0) {
         m.plen[Kg] = tot_pl;
         m.sbeg[Kg] = tot_sb;
     }
 }
-
 
 }  // namespace mms
