@@ -83,13 +83,13 @@ def tune_pairs(mms, torch, x_all, min_log2: int, max_log2: int, reps: int, log=p
         best = None
         for K in FANOUTS:
             for base in PAIR_BASES:
-                mms.set_tuning([(64, K, 4096, 0, base, MMS_PAIRS)])
+                mms.set_tuning([(64, K, 3840, 0, base, MMS_PAIRS)])
                 ws = torch.empty(max(mms.workspace_bytes(n, pairs=True), 256), dtype=torch.uint8, device="cuda")
                 ms = time_pairs(mms, torch, x, v, ok, ov, ws, max(reps, int(2e6 // n)))
                 if best is None or ms < best[0]:
                     best = (ms, K, base)
         ms, K, base = best
-        mms.set_tuning([(64, K, 4096, 0, base, MMS_PAIRS)])
+        mms.set_tuning([(64, K, 3840, 0, base, MMS_PAIRS)])
         ws = torch.empty(max(mms.workspace_bytes(n, pairs=True), 256), dtype=torch.uint8, device="cuda")
         mms.sort_pairs(x, v, out_keys=ok, out_values=ov, i32=False, workspace=ws)
         kk = ok.to(torch.int64) & 0xFFFFFFFF
@@ -101,7 +101,9 @@ def tune_pairs(mms, torch, x_all, min_log2: int, max_log2: int, reps: int, log=p
     return entries
 
 
-def tune(min_log2: int = 8, max_log2: int = 27, reps: int = 5, log=print) -> dict:
+def tune(min_log2: int = 8, max_log2: int = 27, reps: int = 5, log=print, keys_from: dict | None = None) -> dict:
+    """The whole table; with keys_from (a table) only the key-value entries
+    are timed and the keys-only entries are taken from it."""
     import numpy as np
     import torch
 
@@ -111,8 +113,8 @@ def tune(min_log2: int = 8, max_log2: int = 27, reps: int = 5, log=print) -> dic
     n_max = 1 << max_log2
     x_all = torch.from_numpy(mmsgen.uniform_u32(mmsgen.seed_for(6, 0), n_max).view(np.int32)).cuda()
     out_all = torch.empty_like(x_all)
-    entries = []
-    for b in range(min_log2, max_log2 + 1):
+    entries = list(keys_from["entries"]) if keys_from else []
+    for b in range(min_log2, max_log2 + 1) if not keys_from else ():
         n = 1 << b
         x, out = x_all[:n], out_all[:n]
         best = None
@@ -158,8 +160,14 @@ def main(argv=None):
     ap.add_argument("--min-log2", type=int, default=8)
     ap.add_argument("--max-log2", type=int, default=27)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--pairs-only", action="store_true",
+                    help="time the key-value entries only; keep the keys-only entries of --out")
     args = ap.parse_args(argv)
-    table = tune(args.min_log2, args.max_log2, args.reps, log=lambda s: print(s, flush=True))
+    keys_from = None
+    if args.pairs_only:
+        with open(args.out) as f:
+            keys_from = json.load(f)
+    table = tune(args.min_log2, args.max_log2, args.reps, log=lambda s: print(s, flush=True), keys_from=keys_from)
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1)
     print(f"wrote {args.out}", file=sys.stderr)

@@ -201,22 +201,19 @@ __global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundA
         }
         return;
     }
-    if (wave == 0) {   // lane k < Kg: piece k; piece starts by a row prefix sum
-        uint32_t len = 0;
-        if ((uint32_t)lane < Kg) {
-            const uint32_t k = (uint32_t)lane;
-            const uint64_t nk = min(L, glen - (uint64_t)k * L);
-            // the clamps only guard memory safety; exact splits never trigger them
-            const uint32_t s = i == 0 ? 0u : min(table[t * K + k], (uint32_t)nk);
-            const uint32_t e = (obeg + Tout >= glen) ? (uint32_t)nk : min(table[(t + 1) * K + k], (uint32_t)nk);
-            start[k] = s;
-            len = e > s ? e - s : 0u;
-        }
-        const uint32_t incl = row16_incl_sum(len);
-        if ((uint32_t)lane < Kg) seg0[lane + 1] = min(incl, cnt);
-        if (lane == 0) seg0[0] = 0;
+    // Every wave reads the split indices (lane k < Kg: piece k) and lays
+    // the pieces out in registers, so its loads into LDS go out at once;
+    // wave 0 also writes the layout for the merge levels.
+    uint32_t len = 0, st_k = 0;
+    if ((uint32_t)lane < Kg) {
+        const uint32_t k = (uint32_t)lane;
+        const uint64_t nk = min(L, glen - (uint64_t)k * L);
+        // the clamps only guard memory safety; exact splits never trigger them
+        st_k = i == 0 ? 0u : min(table[t * K + k], (uint32_t)nk);
+        const uint32_t e = (obeg + Tout >= glen) ? (uint32_t)nk : min(table[(t + 1) * K + k], (uint32_t)nk);
+        len = e > st_k ? e - st_k : 0u;
     }
-    lds_barrier();
+    const uint32_t incl = min(row16_incl_sum(len), cnt);   // piece k ends at seg0[k + 1]
     {
         // the pieces, concatenated, go into LDS by the memory unit: 64 words
         // (32 elements) of keys (and of values) per instruction, no register
@@ -224,9 +221,9 @@ __global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundA
         // the waves round-robin in piece order
         uint32_t cbase = 0;
         for (uint32_t k = 0; k < Kg; ++k) {
-            const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)seg0[k]);
-            const uint32_t s1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)seg0[k + 1]);
-            const uint32_t st = (uint32_t)__builtin_amdgcn_readfirstlane((int)start[k]);
+            const uint32_t s0 = k ? (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)(k - 1u)) : 0u;
+            const uint32_t s1 = (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)k);
+            const uint32_t st = (uint32_t)__builtin_amdgcn_readlane((int)st_k, (int)k);
             const uint32_t w0 = 2u * s0, w1 = s1 > s0 ? 2u * s1 : w0;   // LDS words of the piece
             const uint32_t nch = (w1 - w0 + 63u) >> 6;
             const uint64_t run0 = 2u * (gb + (uint64_t)k * L + st);   // the piece's first word
@@ -242,8 +239,15 @@ __global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundA
             }
             cbase += nch;
         }
-        vm_drain();
     }
+    if (wave == 0) {
+        if ((uint32_t)lane < Kg) {
+            start[lane] = st_k;
+            seg0[lane + 1] = incl;
+        }
+        if (lane == 0) seg0[0] = 0;
+    }
+    vm_drain();
     lds_barrier();
 
     for (uint32_t lvl = 0; (1u << lvl) < Kg; ++lvl) {
