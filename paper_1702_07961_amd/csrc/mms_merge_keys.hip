@@ -295,6 +295,9 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
         // complete once wave 0 drains its memory counter before storing the
         // next tile's keys below
         const uint64_t t3 = t2 + G;
+        // the waves that build piece tables reach level 0's barrier last:
+        // they issue first until it
+        if (wave < 3) __builtin_amdgcn_s_setprio(2);
         if (wave == 0 && has2 && t3 < tiles) {
             const TileGeo g3 = tile_geo(ph, b, t3, ra, lL);
             uint32_t s3, e3;
@@ -344,9 +347,11 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
                     merge_level_planned<EM>(X, mc.sbeg, mc.plen, mc.plan, g.Kg, lvl, out, wscr, wave, lane);
                 }
                 lds_barrier();
+                if (lvl == 0) __builtin_amdgcn_s_setprio(0);
                 uint32_t* tmp = X; X = Y; Y = tmp;
             }
         }
+        if (g.Kg == 1) __builtin_amdgcn_s_setprio(0);
         if (!has_next) break;
         if (stored) {
             // after the level loop (and its final swap) X holds the next

@@ -129,10 +129,12 @@ __global__ __launch_bounds__(W * 64, 4) void k_merge_pairs(Phase ph, Bufs b, Rou
             cbase += nch;
         }
     }
-    if (wave == 0) {
+    if (wave == 0) {   // the other waves wait for this plan: it issues first
+        __builtin_amdgcn_s_setprio(2);
         build_pieces(mt, s, e, Kg, cnt, lane);
         lds_wave_sync();
         build_plan<W>(mt, Kg, lane);
+        __builtin_amdgcn_s_setprio(0);
     }
     vm_drain();
     lds_barrier();
