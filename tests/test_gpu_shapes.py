@@ -104,3 +104,35 @@ def test_loaded_table_between_buckets(mms):
     for n in [1_500_007, (1 << 21) - 3, (1 << 22) + 1001]:
         x = mmsgen.uniform_u32(mmsgen.seed_for(13, 3 + n % 5), n)
         assert np.array_equal(host(mms.sort(dev(x), i32=False)), oracle.sort(x)), n
+
+
+# key-value sorts: every fan-out and both key-value base shapes (8 x 4 on
+# 2048-pair tiles, 8 x 8 on 4096) on a tie-heavy input at a size where every
+# fan-out runs two or more merge rounds of many 3840-pair tiles, the last
+# group ragged; values are arbitrary words, so a misplaced value shows.
+N_PAIRS_SWEEP = (1 << 22) + 12345
+
+
+@pytest.fixture(scope="module")
+def pairs_input():
+    n = N_PAIRS_SWEEP
+    x = mmsgen.uniform_u32(mmsgen.seed_for(21, 0), n)
+    few = (mmsgen.uniform_u32(mmsgen.seed_for(21, 2), n) % np.uint32(16)) * np.uint32(0x10000001)
+    u = mmsgen.unit_doubles(mmsgen.seed_for(21, 1), n)
+    x = np.where(u < 0.3, few, x).astype(np.uint32)
+    v = mmsgen.uniform_u32(mmsgen.seed_for(21, 3), n)
+    return x, v, oracle.sort(x, v), oracle.sort(x, v, i32=True)
+
+
+@pytest.mark.parametrize("base", [0, 3])
+def test_pairs_shape_sweep(mms, pairs_input, base):
+    x, v, (wku, wvu), (wks, wvs) = pairs_input
+    xd, vd = dev(x), dev(v)
+    for K in FANOUTS:
+        mms.set_tuning([(64, 16, 7168, 3, 4, 0), (64, K, 3840, 0, base, mms.MMS_PAIRS)])
+        p = mms.plan(N_PAIRS_SWEEP, pairs=True)
+        assert p.rounds >= 2 and p.merge_tile == 3840
+        gk, gv = mms.sort_pairs(xd, vd, i32=False)
+        assert np.array_equal(host(gk), wku) and np.array_equal(host(gv), wvu), (K, base, "u32")
+        gk, gv = mms.sort_pairs(xd, vd, i32=True)
+        assert np.array_equal(host(gk), wks) and np.array_equal(host(gv), wvs), (K, base, "i32")
