@@ -26,7 +26,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(PKG, "tuning_mi355x.json")
 
 FANOUTS = [2, 4, 8, 16]   # 32 would need more than 64 probe lanes in the partition
-TILES = [2048, 4096, 6144, 7168, 8192]
+TILES = [2048, 4096, 6144, 7168, 7424, 8192]
 VARIANTS = [0, 1, 2, 3, 4]   # 4: the minBlockHeap merge
 # keys per lane x waves: 8x4, 4x8, 16x2 (2048-key tiles), 8x8, 16x4 (4096), 8x16, 16x8 (8192)
 BASES = [0, 1, 2, 3, 4, 5, 6]

@@ -126,7 +126,7 @@ __device__ __forceinline__ void fetch_rows_async(const uint32_t* __restrict__ ta
 }
 
 // words of one piece table (with its chunk table)
-constexpr uint32_t kMetaWords = 3u * 17u + kPlanWords + (kToutKeys + 4u * kMaxFanout) / 64u + 1u;
+constexpr uint32_t kMetaWords = 3u * 17u + kPlanWords + ((kToutKeys + 4u * kMaxFanout) / 64u + 1u + 3u) / 4u;
 
 // Chunk table from the piece layout: largest k < Kg with sbeg[k] <= 64*c.
 __device__ __forceinline__ void build_chunks(const Meta& m, uint32_t Kg, int lane) {
@@ -138,7 +138,7 @@ __device__ __forceinline__ void build_chunks(const Meta& m, uint32_t Kg, int lan
             if (m.sbeg[mid] <= c * 64u) lo = mid;
             else hi = mid;
         }
-        m.cseg[c] = lo;
+        m.cseg[c] = (uint8_t)lo;
     }
 }
 
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
     uint32_t* mbase = scr + W * Xpose<EM>::WORDS;     // four piece tables of kMetaWords
     auto meta = [&](int which) {
         uint32_t* mb = mbase + kMetaWords * (uint32_t)which;
-        return Meta{mb, mb + 17, mb + 34, mb + 51, mb + 51 + kPlanWords};
+        return Meta{mb, mb + 17, mb + 34, mb + 51, reinterpret_cast<uint8_t*>(mb + 51 + kPlanWords)};
     };
 
     const int lane = threadIdx.x & 63;
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
 
 // Largest merge tile for which two 8-wave workgroups of 64x8-key blocks fit
 // in one compute unit's 160 KiB of LDS.
-constexpr uint32_t kTout2PerCU = 7168;
+constexpr uint32_t kTout2PerCU = 7424;
 
 static hipError_t allow_lds(const void* f, size_t bytes) {
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

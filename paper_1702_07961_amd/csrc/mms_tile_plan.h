@@ -17,7 +17,7 @@ struct Meta {
     uint32_t* plen;
     uint32_t* sbeg;
     uint32_t* plan;   // [4 levels][16 waves][2]: each wave's work per level
-    uint32_t* cseg;   // piece whose LDS slots hold word 64*c (slot coordinates)
+    uint8_t* cseg;    // piece whose LDS slots hold slot 64*c (slot coordinates)
 };
 constexpr uint32_t kPlanWords = 4u * 16u * 2u;
 

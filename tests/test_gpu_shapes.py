@@ -5,7 +5,7 @@ The keys merge has five kernel shapes (variant 0: 64x16-key blocks with 8
 waves, the built-in default; 1: 64x8-key blocks with 16 waves; 2: 64x8 with
 8 waves; 3: as 2 with two workgroups per compute unit; 4: the minBlockHeap
 merge, one heap of 64-key nodes per wave).  Each is run under
-every fan-out K in {2, 4, 8, 16} and merge tiles of 2048, 6144 and 8192 keys,
+every fan-out K in {2, 4, 8, 16} and merge tiles of 2048, 6144, 7424 and 8192 keys,
 on unsigned and signed keys, at a size where every workgroup of the
 persistent grid walks several tiles per round (so the pipeline's prefetch,
 its four-table ring and the buffer swap all run) and the last merge group is
@@ -28,7 +28,7 @@ torch = pytest.importorskip("torch")
 N_SWEEP = (1 << 23) + 12345
 VARIANTS = [0, 1, 2, 3, 4]
 FANOUTS = [2, 4, 8, 16]
-TOUTS = [2048, 6144, 8192]
+TOUTS = [2048, 6144, 7424, 8192]
 # base-case shape per variant (2048-, 4096- and 8192-key tiles all appear)
 BASE_OF_VARIANT = {0: 0, 1: 4, 2: 3, 3: 6, 4: 3}
 
