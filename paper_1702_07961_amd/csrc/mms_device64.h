@@ -4,13 +4,16 @@
 //
 //   E64   a 64-bit key (unsigned order; signed keys are mapped with
 //         key ^ 2^63 on the way in and back on the way out)
-//   E64V  key, tag, 64-bit value.  The tag is the element's position in the
-//         array (or LDS buffer) the pass reads, so (key, tag) is the stable
-//         order and every network sorts stably.
+//   E64T  key and tag.  The tag is the element's slot in the tile as loaded
+//         (the runs sit in LDS in run order), so (key, tag) is the stable
+//         order and every network sorts stably; the values stay in LDS where
+//         they were loaded and are gathered by tag when a tile is stored.
 //
-// Every LDS access below moves one element per lane at consecutive element
-// positions (a fixed function of lane and step plus a wave-uniform base), so
-// the 64-bit traffic is free of bank conflicts whatever the keys.
+// Every LDS access of the networks moves one element per lane at
+// consecutive element positions (a fixed function of lane and step plus a
+// wave-uniform base), so their traffic is free of bank conflicts whatever
+// the keys; only the final gather of values by tag reads data-dependent
+// addresses.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -32,15 +35,14 @@ struct E64 {
     uint64_t k;
     __device__ static E64 sentinel() { return {kSentKey64}; }
 };
-struct E64V {
+struct E64T {
     uint64_t k;
     uint32_t t;
-    uint64_t v;
-    __device__ static E64V sentinel() { return {kSentKey64, kSentTag, 0ull}; }
+    __device__ static E64T sentinel() { return {kSentKey64, kSentTag}; }
 };
 
 __device__ __forceinline__ bool before(const E64& a, const E64& b) { return a.k < b.k; }
-__device__ __forceinline__ bool before(const E64V& a, const E64V& b) {
+__device__ __forceinline__ bool before(const E64T& a, const E64T& b) {
     return a.k < b.k || (a.k == b.k && a.t < b.t);
 }
 
@@ -50,11 +52,11 @@ __device__ __forceinline__ void cex(E64& lo, E64& hi) {
     lo.k = sw ? b : a;
     hi.k = sw ? a : b;
 }
-__device__ __forceinline__ void cex(E64V& lo, E64V& hi) {
+__device__ __forceinline__ void cex(E64T& lo, E64T& hi) {
     const bool sw = before(hi, lo);
-    const E64V a = lo, b = hi;
-    lo.k = sw ? b.k : a.k; lo.t = sw ? b.t : a.t; lo.v = sw ? b.v : a.v;
-    hi.k = sw ? a.k : b.k; hi.t = sw ? a.t : b.t; hi.v = sw ? a.v : b.v;
+    const E64T a = lo, b = hi;
+    lo.k = sw ? b.k : a.k; lo.t = sw ? b.t : a.t;
+    hi.k = sw ? a.k : b.k; hi.t = sw ? a.t : b.t;
 }
 
 // keep the earlier (want_first) or the later of `mine` and `other`
@@ -62,10 +64,10 @@ __device__ __forceinline__ E64 pick(const E64& mine, const E64& other, bool want
     const bool other_first = other.k < mine.k;
     return {(want_first ? other_first : !other_first) ? other.k : mine.k};
 }
-__device__ __forceinline__ E64V pick(const E64V& mine, const E64V& other, bool want_first) {
+__device__ __forceinline__ E64T pick(const E64T& mine, const E64T& other, bool want_first) {
     const bool other_first = before(other, mine);
     const bool take = want_first ? other_first : !other_first;
-    return {take ? other.k : mine.k, take ? other.t : mine.t, take ? other.v : mine.v};
+    return {take ? other.k : mine.k, take ? other.t : mine.t};
 }
 
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
@@ -74,11 +76,12 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
     return ((uint64_t)hi << 32) | lo;
 }
 __device__ __forceinline__ E64 shfl_xor(const E64& e, int m) { return {shfl_xor_u64(e.k, m)}; }
-__device__ __forceinline__ E64V shfl_xor(const E64V& e, int m) {
-    return {shfl_xor_u64(e.k, m), shfl_xor_u32(e.t, m), shfl_xor_u64(e.v, m)};
+__device__ __forceinline__ E64T shfl_xor(const E64T& e, int m) {
+    return {shfl_xor_u64(e.k, m), shfl_xor_u32(e.t, m)};
 }
 
-// LDS views of a 64-bit merge buffer (see LdsKV32)
+// LDS views of a 64-bit merge buffer: key(i) and get(i) read slot i, put(i, e)
+// writes it (the interface merge_level reads and writes through).
 struct LdsK64 {
     using El = E64;
     uint64_t* k;
@@ -86,15 +89,24 @@ struct LdsK64 {
     __device__ __forceinline__ El get(uint32_t i) const { return {k[i]}; }
     __device__ __forceinline__ void put(uint32_t i, const El& e) const { k[i] = e.k; }
 };
-struct LdsKV64 {
-    using El = E64V;
+// Key-value merge levels: level 0 reads the keys as loaded, each element's
+// tag being its own slot; later levels read keys and 16-bit tags written by
+// the level before (tile slots stay below 2^16).
+struct LdsKT64Loaded {
+    using El = E64T;
     uint64_t* k;
-    uint64_t* v;
     __device__ __forceinline__ uint64_t key(uint32_t i) const { return k[i]; }
-    __device__ __forceinline__ El get(uint32_t i) const { return {k[i], i, v[i]}; }
+    __device__ __forceinline__ El get(uint32_t i) const { return {k[i], i}; }
+};
+struct LdsKT64 {
+    using El = E64T;
+    uint64_t* k;
+    uint16_t* t;
+    __device__ __forceinline__ uint64_t key(uint32_t i) const { return k[i]; }
+    __device__ __forceinline__ El get(uint32_t i) const { return {k[i], t[i]}; }
     __device__ __forceinline__ void put(uint32_t i, const El& e) const {
         k[i] = e.k;
-        v[i] = e.v;
+        t[i] = (uint16_t)e.t;
     }
 };
 
@@ -108,15 +120,16 @@ struct GlobalSinkK64 {
         if (i < lim) gptr64(k)[i] = e.k ^ flip;
     }
 };
-struct GlobalSinkKV64 {
+struct GlobalSinkKT64 {
     uint64_t* k;
     uint64_t* v;
+    const uint64_t* V;   // LDS values, by slot as loaded
     uint64_t flip;
     uint32_t lim;
-    __device__ __forceinline__ void put(uint32_t i, const E64V& e) const {
+    __device__ __forceinline__ void put(uint32_t i, const E64T& e) const {
         if (i < lim) {
             gptr64(k)[i] = e.k ^ flip;
-            gptr64(v)[i] = e.v;
+            gptr64(v)[i] = V[e.t];
         }
     }
 };

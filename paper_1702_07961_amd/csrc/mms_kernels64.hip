@@ -10,9 +10,9 @@
 //                 the pieces are loaded back to back and merged pairwise in
 //                 log2 K levels of conflict-free block merges
 //
-// Pairs carry (key, tag, value) through every network, the tag being the
-// element's position in the array or LDS buffer the pass reads, so every
-// step is stable and no step gathers by a data-dependent LDS address.
+// Pairs carry (key, tag) through every network, the tag being the element's
+// slot in the tile as loaded, so every step is stable; the values stay in LDS
+// where they were loaded and are gathered by tag when a tile is stored.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -27,9 +27,14 @@ namespace mms {
 
 namespace {
 
-// LDS of one exchange buffer of the base case: keys, then (pairs) values and
-// tags, for T elements
-template <bool PAIRS> constexpr uint32_t xbuf_bytes(uint32_t T) { return T * (PAIRS ? 20u : 8u); }
+// LDS of one exchange buffer of the base case: keys, then (pairs) tags, for
+// T elements
+template <bool PAIRS> constexpr uint32_t xbuf_bytes(uint32_t T) { return T * (PAIRS ? 12u : 8u); }
+// LDS of the base case: (pairs) the values as loaded, then two exchange
+// buffers
+template <bool PAIRS> constexpr uint32_t tile_lds_bytes(uint32_t T) {
+    return (PAIRS ? 8u * T : 0u) + 2u * xbuf_bytes<PAIRS>(T);
+}
 
 }  // namespace
 
@@ -44,10 +49,12 @@ template <bool PAIRS> constexpr uint32_t xbuf_bytes(uint32_t T) { return T * (PA
 // ===========================================================================
 template <int E, int W, bool PAIRS>
 __global__ __launch_bounds__(W * 64) void k_tile_sort64(Phase64 ph, Bufs64 b, uint64_t flip) {
-    using El = std::conditional_t<PAIRS, E64V, E64>;
+    using El = std::conditional_t<PAIRS, E64T, E64>;
     constexpr uint32_t CH = 64u * E;
     constexpr uint32_t T = CH * W;
     extern __shared__ __align__(16) uint64_t smem64[];
+    uint64_t* V = smem64;                                       // pairs: values by slot
+    uint8_t* xbase = reinterpret_cast<uint8_t*>(smem64 + (PAIRS ? T : 0u));
 
     const int lane = threadIdx.x & 63;
     const uint32_t ul = (uint32_t)lane;
@@ -63,8 +70,12 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort64(Phase64 ph, Bufs64 b, ui
     for (int e = 0; e < E; ++e) {
         const uint32_t j = (uint32_t)wave * CH + (uint32_t)e * 64u + ul;
         if (j < cnt) {
-            if constexpr (PAIRS) r[e] = El{gptr64(b.in_k)[base + j] ^ flip, j, gptr64(b.in_v)[base + j]};
-            else r[e] = El{gptr64(b.in_k)[base + j] ^ flip};
+            if constexpr (PAIRS) {
+                r[e] = El{gptr64(b.in_k)[base + j] ^ flip, j};
+                V[j] = gptr64(b.in_v)[base + j];
+            } else {
+                r[e] = El{gptr64(b.in_k)[base + j] ^ flip};
+            }
         } else {
             r[e] = El::sentinel();
         }
@@ -73,20 +84,16 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort64(Phase64 ph, Bufs64 b, ui
 
     uint32_t buf = 0;
     auto exchange = [&](int pw, bool mirror, bool want_first) {
-        uint8_t* X = reinterpret_cast<uint8_t*>(smem64) + buf * xbuf_bytes<PAIRS>(T);
+        uint8_t* X = xbase + buf * xbuf_bytes<PAIRS>(T);
         buf ^= 1u;
         uint64_t* xk = reinterpret_cast<uint64_t*>(X);
-        uint64_t* xv = xk + T;
-        uint32_t* xt = reinterpret_cast<uint32_t*>(xv + T);
+        uint32_t* xt = reinterpret_cast<uint32_t*>(xk + T);
         const uint32_t me = (uint32_t)wave * CH;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const uint32_t slot = me + (uint32_t)e * 64u + ul;
             xk[slot] = r[e].k;
-            if constexpr (PAIRS) {
-                xv[slot] = r[e].v;
-                xt[slot] = r[e].t;
-            }
+            if constexpr (PAIRS) xt[slot] = r[e].t;
         }
         lds_barrier();
         const uint32_t them = (uint32_t)pw * CH;
@@ -94,7 +101,7 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort64(Phase64 ph, Bufs64 b, ui
         for (int e = 0; e < E; ++e) {
             const uint32_t slot = them + (mirror ? (uint32_t)(E - 1 - e) * 64u + (63u - ul) : (uint32_t)e * 64u + ul);
             El o;
-            if constexpr (PAIRS) o = El{xk[slot], xt[slot], xv[slot]};
+            if constexpr (PAIRS) o = El{xk[slot], xt[slot]};
             else o = El{xk[slot]};
             r[e] = pick(r[e], o, want_first);
         }
@@ -118,13 +125,13 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort64(Phase64 ph, Bufs64 b, ui
         const uint32_t pos = p0 + (uint32_t)e;
         if (vec && pos + 2u <= cnt) {
             *reinterpret_cast<gu64x2*>(gptr64(out_k) + pos) = u64x2{r[e].k ^ flip_out, r[e + 1].k ^ flip_out};
-            if constexpr (PAIRS) *reinterpret_cast<gu64x2*>(gptr64(out_v) + pos) = u64x2{r[e].v, r[e + 1].v};
+            if constexpr (PAIRS) *reinterpret_cast<gu64x2*>(gptr64(out_v) + pos) = u64x2{V[r[e].t], V[r[e + 1].t]};
         } else {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 if (pos + (uint32_t)j < cnt) {
                     gptr64(out_k)[pos + j] = r[e + j].k ^ flip_out;
-                    if constexpr (PAIRS) gptr64(out_v)[pos + j] = r[e + j].v;
+                    if constexpr (PAIRS) gptr64(out_v)[pos + j] = V[r[e + j].t];
                 }
             }
         }
@@ -169,11 +176,15 @@ __global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundA
     const uint32_t Tout = ra.Tout, K = ra.K;
     const uint64_t L = ra.L;
     extern __shared__ __align__(16) uint64_t smem64[];
+    // keys of the level buffers; pairs: their 16-bit tags and the values by
+    // slot as loaded
     uint64_t* Xk = smem64;
     uint64_t* Yk = smem64 + Tout;
-    uint64_t* Xv = PAIRS ? smem64 + 2 * Tout : nullptr;
-    uint64_t* Yv = PAIRS ? smem64 + 3 * Tout : nullptr;
-    uint32_t* seg0 = reinterpret_cast<uint32_t*>(smem64 + (PAIRS ? 4u : 2u) * Tout);   // [kMaxFanout + 1]
+    uint64_t* V = PAIRS ? smem64 + 2 * Tout : nullptr;
+    uint16_t* Xt = PAIRS ? reinterpret_cast<uint16_t*>(smem64 + 3 * Tout) : nullptr;
+    uint16_t* Yt = PAIRS ? Xt + Tout : nullptr;
+    uint32_t* seg0 = PAIRS ? reinterpret_cast<uint32_t*>(Yt + Tout)
+                           : reinterpret_cast<uint32_t*>(smem64 + 2u * Tout);   // [kMaxFanout + 1]
     uint32_t* start = seg0 + kMaxFanout + 1;                                            // [kMaxFanout]
 
     const int lane = threadIdx.x & 63;
@@ -234,7 +245,7 @@ __global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundA
                               reinterpret_cast<uint32_t*>(Xk) + j0);
                     if constexpr (PAIRS)
                         dma_dword(reinterpret_cast<const uint32_t*>(src_v) + run0 + 64u * c, (uint32_t)lane,
-                                  reinterpret_cast<uint32_t*>(Xv) + j0);
+                                  reinterpret_cast<uint32_t*>(V) + j0);
                 }
             }
             cbase += nch;
@@ -253,10 +264,16 @@ __global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundA
     for (uint32_t lvl = 0; (1u << lvl) < Kg; ++lvl) {
         const bool last = (2u << lvl) >= Kg;
         if constexpr (PAIRS) {
-            const LdsKV64 X{Xk, Xv};
-            if (last) merge_level<EM>(X, seg0, Kg, lvl, cnt, GlobalSinkKV64{dst_k + obase, dst_v + obase, flip_out, cnt},
-                                      wave, W, lane);
-            else merge_level<EM>(X, seg0, Kg, lvl, cnt, LdsKV64{Yk, Yv}, wave, W, lane);
+            const GlobalSinkKT64 gout{dst_k + obase, dst_v + obase, V, flip_out, cnt};
+            if (lvl == 0) {
+                const LdsKT64Loaded X{Xk};
+                if (last) merge_level<EM>(X, seg0, Kg, lvl, cnt, gout, wave, W, lane);
+                else merge_level<EM>(X, seg0, Kg, lvl, cnt, LdsKT64{Yk, Yt}, wave, W, lane);
+            } else {
+                const LdsKT64 X{Xk, Xt};
+                if (last) merge_level<EM>(X, seg0, Kg, lvl, cnt, gout, wave, W, lane);
+                else merge_level<EM>(X, seg0, Kg, lvl, cnt, LdsKT64{Yk, Yt}, wave, W, lane);
+            }
         } else {
             const LdsK64 X{Xk};
             if (last) merge_level<EM>(X, seg0, Kg, lvl, cnt, GlobalSinkK64{dst_k + obase, flip_out, cnt}, wave, W, lane);
@@ -264,7 +281,7 @@ __global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundA
         }
         lds_barrier();
         uint64_t* tmp = Xk; Xk = Yk; Yk = tmp;
-        tmp = Xv; Xv = Yv; Yv = tmp;
+        uint16_t* tt = Xt; Xt = Yt; Yt = tt;
     }
 }
 
@@ -280,14 +297,14 @@ hipError_t launch_tile_sort64(bool pairs, const Phase64& ph, const Bufs64& b, ui
     if (pairs) {
         constexpr int E = 8, W = 4;
         static_assert(64u * E * W == kT64Pairs, "pairs base tile");
-        const size_t lds = 2u * xbuf_bytes<true>(kT64Pairs);
+        const size_t lds = tile_lds_bytes<true>(kT64Pairs);
         hipError_t e = allow_lds64((const void*)k_tile_sort64<E, W, true>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_tile_sort64<E, W, true>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, flip);
     } else {
         constexpr int E = 8, W = 8;
         static_assert(64u * E * W == kT64Keys, "keys base tile");
-        const size_t lds = 2u * xbuf_bytes<false>(kT64Keys);
+        const size_t lds = tile_lds_bytes<false>(kT64Keys);
         hipError_t e = allow_lds64((const void*)k_tile_sort64<E, W, false>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_tile_sort64<E, W, false>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, flip);
@@ -308,7 +325,8 @@ hipError_t launch_merge64(bool pairs, const Phase64& ph, const Bufs64& b, const 
     if (ph.tiles == 0) return hipSuccess;
     if (ra.K > kMaxFanout || ra.Tout > (pairs ? kTout64Pairs : kTout64Keys)) return hipErrorInvalidValue;
     constexpr int W = 8;
-    const size_t lds = (pairs ? 4u : 2u) * ra.Tout * sizeof(uint64_t) + (2u * kMaxFanout + 4u) * sizeof(uint32_t);
+    // keys 2 x Tout; pairs: values Tout and 16-bit tags 2 x Tout more
+    const size_t lds = (pairs ? 28u : 16u) * ra.Tout + (2u * kMaxFanout + 4u) * sizeof(uint32_t);
     const void* f = pairs ? (const void*)k_merge64<W, true> : (const void*)k_merge64<W, false>;
     hipError_t e = allow_lds64(f, lds);
     if (e != hipSuccess) return e;
