@@ -165,13 +165,13 @@ __global__ __launch_bounds__(256) void k_corank_tiles64(Phase64 ph, Bufs64 b, Ro
 // K-way merge of one output tile (§4.2, §7): the tile's pieces of its
 // group's runs, bounded by the split indices of its first and last output,
 // are loaded into LDS back to back, merged pairwise level by level (log2 K
-// levels, 64x8-element blocks, every wave an equal share of each level's
+// levels, 64x8-key or 64x4-pair blocks, every wave an equal share of each level's
 // outputs), and the last level is written to memory.
 // ===========================================================================
 template <int W, bool PAIRS>
 __global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundArgs ra,
                                                     const uint32_t* __restrict__ table, uint64_t flip) {
-    constexpr int EM = 8;
+    constexpr int EM = PAIRS ? 4 : 8;   // a wave's share of a level: 256 pairs or 512 keys
     constexpr uint32_t NT = W * 64u;
     const uint32_t Tout = ra.Tout, K = ra.K;
     const uint64_t L = ra.L;
