@@ -1,4 +1,5 @@
-// Key-value building blocks: a (key, tag) pair as one 64-bit word.
+// 64-bit words in the transposed block merge: a (key, tag) pair packed into
+// one word for the key-value sorts, or a 64-bit key.
 //
 // The merge and base case of the key-value sort order the pairs (key, tag),
 // tag being an element's slot in the tile as loaded, which is the stable
@@ -18,6 +19,7 @@
 #include <stdint.h>
 
 #include "mms_device.h"
+#include "mms_tile_plan.h"
 
 namespace mms {
 
@@ -55,13 +57,38 @@ __device__ __forceinline__ void cex_kt(double& lo, double& hi) {
     hi = kt_max(a, b);
 }
 
-template <int EM>
-__device__ __forceinline__ void reg_stages_kt(double (&m)[EM]) {
+// The transposed block merge below runs on any 64-bit word with these
+// operations: packed (key, tag) doubles, or 64-bit keys (unsigned order, a
+// compare and two selects per compare-exchange half).
+__device__ __forceinline__ uint32_t w_hi(double x) { return kt_hi(x); }
+__device__ __forceinline__ uint32_t w_lo(double x) { return kt_lo(x); }
+__device__ __forceinline__ uint32_t w_hi(uint64_t x) { return (uint32_t)(x >> 32); }
+__device__ __forceinline__ uint32_t w_lo(uint64_t x) { return (uint32_t)x; }
+template <class T> __device__ __forceinline__ T w_join(uint32_t hi, uint32_t lo);
+template <> __device__ __forceinline__ double w_join<double>(uint32_t hi, uint32_t lo) { return kt_join(hi, lo); }
+template <> __device__ __forceinline__ uint64_t w_join<uint64_t>(uint32_t hi, uint32_t lo) {
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ void w_cex(double& lo, double& hi) { cex_kt(lo, hi); }
+__device__ __forceinline__ void w_cex(uint64_t& lo, uint64_t& hi) {
+    const uint64_t a = lo, b = hi;
+    const bool sw = b < a;
+    lo = sw ? b : a;
+    hi = sw ? a : b;
+}
+__device__ __forceinline__ double w_min(double a, double b) { return kt_min(a, b); }
+__device__ __forceinline__ uint64_t w_min(uint64_t a, uint64_t b) { return b < a ? b : a; }
+template <class T> __device__ __forceinline__ T w_sentinel();
+template <> __device__ __forceinline__ double w_sentinel<double>() { return kt_sentinel(); }
+template <> __device__ __forceinline__ uint64_t w_sentinel<uint64_t>() { return ~0ull; }
+
+template <int EM, class T>
+__device__ __forceinline__ void reg_stages_kt(T (&m)[EM]) {
 #pragma unroll
     for (int d = EM / 2; d >= 1; d >>= 1) {
 #pragma unroll
         for (int e = 0; e < EM; ++e)
-            if ((e & d) == 0) cex_kt(m[e], m[e | d]);
+            if ((e & d) == 0) w_cex(m[e], m[e | d]);
     }
 }
 
@@ -84,8 +111,8 @@ __device__ __forceinline__ void xpose_half(uint32_t (&h)[EM], uint32_t* scr, Wr 
 // position c*256 + 4*lane + j), with the index moves of block_sort_keys and
 // the same conflict-free scratch pattern, each transpose done once for the
 // high and once for the low words.
-template <int EM>
-__device__ __forceinline__ void block_sort_kt(double (&m)[EM], uint32_t* scr, int lane) {
+template <int EM, class T>
+__device__ __forceinline__ void block_sort_kt(T (&m)[EM], uint32_t* scr, int lane) {
     static_assert(EM == 8, "64x8-pair blocks");
     constexpr uint32_t RS = Xpose<EM>::RS;
     const uint32_t ul = (uint32_t)lane;
@@ -94,8 +121,8 @@ __device__ __forceinline__ void block_sort_kt(double (&m)[EM], uint32_t* scr, in
     uint32_t hi[EM], lo[EM];
 #pragma unroll
     for (int e = 0; e < EM; ++e) {
-        hi[e] = kt_hi(m[e]);
-        lo[e] = kt_lo(m[e]);
+        hi[e] = w_hi(m[e]);
+        lo[e] = w_lo(m[e]);
     }
     const uint32_t tb = (ul >> 3) * RS + (ul & 7u);      // lane = (bits 8..6, bits 2..0)
     auto s_at = [&](int e) { return (uint32_t)e * RS + ul; };
@@ -103,12 +130,12 @@ __device__ __forceinline__ void block_sort_kt(double (&m)[EM], uint32_t* scr, in
     xpose_half<EM>(hi, scr, s_at, t_at);
     xpose_half<EM>(lo, scr, s_at, t_at);
 #pragma unroll
-    for (int e = 0; e < EM; ++e) m[e] = kt_join(hi[e], lo[e]);
+    for (int e = 0; e < EM; ++e) m[e] = w_join<T>(hi[e], lo[e]);
     reg_stages_kt<EM>(m);                                // index bits 5..3
 #pragma unroll
     for (int e = 0; e < EM; ++e) {
-        hi[e] = kt_hi(m[e]);
-        lo[e] = kt_lo(m[e]);
+        hi[e] = w_hi(m[e]);
+        lo[e] = w_lo(m[e]);
     }
     const uint32_t fb = (ul >> 4) * RS + 4u * (ul & 15u);
     auto to_f = [&](uint32_t (&h)[EM]) {
@@ -138,15 +165,15 @@ __device__ __forceinline__ void block_sort_kt(double (&m)[EM], uint32_t* scr, in
     }
 #pragma unroll
     for (int e = 0; e < EM; ++e) {
-        const double a = kt_join(hi[e], lo[e]), o = kt_join(oh[e], ol[e]);
+        const T a = w_join<T>(hi[e], lo[e]), o = w_join<T>(oh[e], ol[e]);
         m[e] = ((o < a) != keep_max) ? o : a;   // one compare, two selects
     }
 #pragma unroll
     for (int c = 0; c < EM / 4; ++c) {                   // index bits 1..0
-        cex_kt(m[4 * c + 0], m[4 * c + 2]);
-        cex_kt(m[4 * c + 1], m[4 * c + 3]);
-        cex_kt(m[4 * c + 0], m[4 * c + 1]);
-        cex_kt(m[4 * c + 2], m[4 * c + 3]);
+        w_cex(m[4 * c + 0], m[4 * c + 2]);
+        w_cex(m[4 * c + 1], m[4 * c + 3]);
+        w_cex(m[4 * c + 0], m[4 * c + 1]);
+        w_cex(m[4 * c + 2], m[4 * c + 3]);
     }
 }
 
@@ -169,14 +196,14 @@ __device__ __forceinline__ ElemKT shfl_xor(const ElemKT& e, int m) {
 // Number of block positions k with a_k < b_k (a increasing and b
 // decreasing in k, so they form a prefix): a binary search over the
 // registers' last lanes, as prefix_len does for keys.
-template <int LO, int HI, int EM>
-__device__ __forceinline__ uint32_t prefix_len_kt(const double (&a)[EM], const double (&b)[EM]) {
+template <int LO, int HI, int EM, class T>
+__device__ __forceinline__ uint32_t prefix_len_kt(const T (&a)[EM], const T (&b)[EM]) {
     if constexpr (HI - LO == 1) {
         return (uint32_t)LO * 64u + (uint32_t)__popcll(__ballot(a[LO] < b[LO]));
     } else {
         constexpr int MID = (LO + HI) / 2;
-        if (__ballot(a[MID - 1] < b[MID - 1]) >> 63) return prefix_len_kt<MID, HI, EM>(a, b);
-        return prefix_len_kt<LO, MID, EM>(a, b);
+        if (__ballot(a[MID - 1] < b[MID - 1]) >> 63) return prefix_len_kt<MID, HI, EM, T>(a, b);
+        return prefix_len_kt<LO, MID, EM, T>(a, b);
     }
 }
 
@@ -187,6 +214,7 @@ __device__ __forceinline__ uint32_t prefix_len_kt(const double (&a)[EM], const d
 // returns the key and tag unpacked, so a block's reads can all be issued
 // before the first is used.
 struct KtSrcLoaded {
+    using Word = double;
     const uint32_t* k;
     struct Cur {
         const uint32_t* k;
@@ -197,6 +225,10 @@ struct KtSrcLoaded {
         }
     };
     __device__ __forceinline__ Cur from(uint32_t i) const { return {k + i, i}; }
+    __device__ __forceinline__ uint32_t corank(uint32_t aA, uint32_t la, uint32_t aB, uint32_t lb, uint32_t d,
+                                               int lane) const {
+        return lds_corank2(k, aA, la, aB, lb, d, lane);
+    }
     // pairs i .. i+3 (i a multiple of 4)
     __device__ __forceinline__ void at4(uint32_t i, double* r) const {
         const uint4 v = *reinterpret_cast<const uint4*>(k + i);
@@ -207,6 +239,7 @@ struct KtSrcLoaded {
     }
 };
 struct KtSrcTagged {
+    using Word = double;
     const uint32_t* k;
     const uint16_t* t;
     struct Cur {
@@ -218,6 +251,10 @@ struct KtSrcTagged {
         }
     };
     __device__ __forceinline__ Cur from(uint32_t i) const { return {k + i, t + i}; }
+    __device__ __forceinline__ uint32_t corank(uint32_t aA, uint32_t la, uint32_t aB, uint32_t lb, uint32_t d,
+                                               int lane) const {
+        return lds_corank2(k, aA, la, aB, lb, d, lane);
+    }
     __device__ __forceinline__ void at4(uint32_t i, double* r) const {
         const uint4 v = *reinterpret_cast<const uint4*>(k + i);
         const uint2 w = *reinterpret_cast<const uint2*>(t + i);
@@ -311,13 +348,16 @@ __device__ __forceinline__ void read_block(const Cur& A, const Cur& B, double (&
 }
 
 // Merge outputs [d0, d1) of A = X[aA, aA+la) and B = X[aB, aB+lb) in blocks
-// of N = 64*EM pairs, the key-value form of merge_pair_range_keys: A holds
-// the smaller tags, so the split on keys with A first on ties is the split
-// of the pair order.  out_base + d0 must be a multiple of 4.
+// of N = 64*EM words, the 64-bit form of merge_pair_range_keys.  For packed
+// (key, tag) pairs A holds the smaller tags, so the split on keys with A
+// first on ties is the split of the pair order; for 64-bit keys a key equal
+// to the sentinel stands in for it, as in the 32-bit keys merge.
+// out_base + d0 must be a multiple of 4.
 template <int EM, class Src, class Sink>
 __device__ __forceinline__ void merge_pair_range_kt(const Src& X, uint32_t aA, uint32_t la, uint32_t aB, uint32_t lb,
                                                     uint32_t d0, uint32_t d1, const Sink& out, uint32_t out_base,
                                                     uint32_t* scr, int lane) {
+    using T = typename Src::Word;
     constexpr uint32_t N = (uint32_t)kWave * EM;
     if (la == 0 || lb == 0) {
         // one run is empty: the other is already in order; move it in the
@@ -325,53 +365,163 @@ __device__ __forceinline__ void merge_pair_range_kt(const Src& X, uint32_t aA, u
         // not stored)
         const uint32_t a0 = lb == 0 ? aA : aB;
         for (uint32_t o = d0; o < d1; o += N) {
-            double m[EM];
+            T m[EM];
 #pragma unroll
             for (int c = 0; c < EM / 4; ++c) X.at4(a0 + o + (uint32_t)c * 256u + 4u * (uint32_t)lane, m + 4 * c);
             out.template put_block<EM>(out_base + o, min(N, d1 - o), m, lane);
         }
         return;
     }
-    uint32_t p = lds_corank2(X.k, aA, la, aB, lb, d0, lane);
+    uint32_t p = X.corank(aA, la, aB, lb, d0, lane);
     uint32_t q = d0 - p;
     for (uint32_t o = d0; o < d1; o += N) {
-        double m[EM];
+        T m[EM];
         uint32_t u;
         if (p + N <= la && q + N <= lb) {
             // b's reads from its lowest position up, so every address is a
             // base plus a constant offset
             const auto A = X.from(aA + p + (uint32_t)lane);
             const auto B = X.from(aB + q + (N - 1u) - (uint32_t)lane - (uint32_t)(EM - 1) * kWave);
-            double a[EM], b[EM];
+            T a[EM], b[EM];
             read_block<EM>(A, B, a, b);
 #pragma unroll
-            for (int e = 0; e < EM; ++e) m[e] = kt_min(a[e], b[e]);
-            u = prefix_len_kt<0, EM, EM>(a, b);
+            for (int e = 0; e < EM; ++e) m[e] = w_min(a[e], b[e]);
+            u = prefix_len_kt<0, EM, EM, T>(a, b);
         } else {
             // near the end of a run: the same reads, then the sentinel for
             // every position past a run's end.  Those reads stay below the
             // end of the last run plus N, inside the caller's LDS; what they
-            // return is discarded.  The sentinel is above every pair, so
-            // the cursors only pass a run's end in the tile's last block.
+            // return is discarded.  Only positions where a is strictly below
+            // b count as taken from A, so the A cursor stays inside its run
+            // and the B cursor passes its end only in the range's last
+            // block.
             const uint32_t pc = min(p, la), qc = min(q, lb);
             const auto A = X.from(aA + pc + (uint32_t)lane);
             const auto B = X.from(aB + qc + (N - 1u) - (uint32_t)lane - (uint32_t)(EM - 1) * kWave);
             const uint32_t ra = la - pc, rb = lb - qc;
-            double a[EM], b[EM];
+            T a[EM], b[EM];
             read_block<EM>(A, B, a, b);
 #pragma unroll
             for (int e = 0; e < EM; ++e) {
                 const uint32_t k = (uint32_t)e * kWave + (uint32_t)lane;
-                a[e] = k < ra ? a[e] : kt_sentinel();
-                b[e] = N - 1u - k < rb ? b[e] : kt_sentinel();
-                m[e] = kt_min(a[e], b[e]);
+                a[e] = k < ra ? a[e] : w_sentinel<T>();
+                b[e] = N - 1u - k < rb ? b[e] : w_sentinel<T>();
+                m[e] = w_min(a[e], b[e]);
             }
-            u = prefix_len_kt<0, EM, EM>(a, b);
+            u = prefix_len_kt<0, EM, EM, T>(a, b);
         }
         block_sort_kt<EM>(m, scr, lane);
         out.template put_block<EM>(out_base + o, min(N, d1 - o), m, lane);
         p = (uint32_t)__builtin_amdgcn_readfirstlane((int)(p + u));
         q = (uint32_t)__builtin_amdgcn_readfirstlane((int)(q + N - u));
+    }
+}
+
+// 64-bit keys: one LDS array of words, and the sinks of a sorted block in
+// layout F (block position t = c*256 + 4*lane + j, four consecutive words per
+// lane and c: two 16-byte accesses).
+struct U64Src {
+    using Word = uint64_t;
+    const uint64_t* k;
+    struct Cur {
+        const uint64_t* k;
+    };
+    __device__ __forceinline__ Cur from(uint32_t i) const { return {k + i}; }
+    __device__ __forceinline__ uint64_t key(uint32_t i) const { return k[i]; }
+    __device__ __forceinline__ void at4(uint32_t i, uint64_t* r) const {
+        const ulonglong2 v0 = *reinterpret_cast<const ulonglong2*>(k + i);
+        const ulonglong2 v1 = *reinterpret_cast<const ulonglong2*>(k + i + 2);
+        r[0] = v0.x;
+        r[1] = v0.y;
+        r[2] = v1.x;
+        r[3] = v1.y;
+    }
+    __device__ __forceinline__ uint32_t corank(uint32_t aA, uint32_t la, uint32_t aB, uint32_t lb, uint32_t d,
+                                               int lane) const {
+        return lds_corank2_view(*this, aA, la, aB, lb, d, lane);
+    }
+};
+template <int EM>
+__device__ __forceinline__ void read_block(const U64Src::Cur& A, const U64Src::Cur& B, uint64_t (&a)[EM],
+                                           uint64_t (&b)[EM]) {
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+        a[e] = A.k[(uint32_t)e * kWave];
+        b[e] = B.k[(uint32_t)(EM - 1 - e) * kWave];
+    }
+}
+struct U64SinkLds {
+    uint64_t* k;
+    template <int EM>
+    __device__ __forceinline__ void put_block(uint32_t pos0, uint32_t cnt, const uint64_t (&m)[EM], int lane) const {
+#pragma unroll
+        for (int c = 0; c < EM / 4; ++c) {
+            const uint32_t p = (uint32_t)c * 256u + 4u * (uint32_t)lane;
+            const uint64_t* r = m + 4 * c;
+            if (p + 4u <= cnt) {
+                *reinterpret_cast<ulonglong2*>(k + pos0 + p) = make_ulonglong2(r[0], r[1]);
+                *reinterpret_cast<ulonglong2*>(k + pos0 + p + 2) = make_ulonglong2(r[2], r[3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (p + (uint32_t)j < cnt) k[pos0 + p + j] = r[j];
+            }
+        }
+    }
+};
+struct U64SinkGlobal {
+    uint64_t* k;         // tile output base
+    uint64_t flip;
+    uint32_t lim;        // positions >= lim are not stored
+    bool vec;            // k is 16-byte aligned
+    template <int EM>
+    __device__ __forceinline__ void put_block(uint32_t pos0, uint32_t cnt, const uint64_t (&m)[EM], int lane) const {
+        typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+        typedef __attribute__((address_space(1))) u64x2 gu64x2_t;
+        typedef __attribute__((address_space(1))) uint64_t gu64_t;
+        const uint32_t c_lim = min(cnt, lim > pos0 ? lim - pos0 : 0u);
+        gu64_t* g = (gu64_t*)k;
+#pragma unroll
+        for (int c = 0; c < EM / 4; ++c) {
+            const uint32_t p = (uint32_t)c * 256u + 4u * (uint32_t)lane;
+            const uint64_t* r = m + 4 * c;
+            if (vec && p + 4u <= c_lim) {
+                *reinterpret_cast<gu64x2_t*>(g + pos0 + p) = u64x2{r[0] ^ flip, r[1] ^ flip};
+                *reinterpret_cast<gu64x2_t*>(g + pos0 + p + 2) = u64x2{r[2] ^ flip, r[3] ^ flip};
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (p + (uint32_t)j < c_lim) g[pos0 + p + j] = r[j] ^ flip;
+            }
+        }
+    }
+};
+
+// One planned merge level (the plan's encoding as in the keys merge).
+template <int EM, class Src, class Sink>
+__device__ __forceinline__ void merge_level_kt(const Src& X, const Meta& mt, uint32_t nseg0, uint32_t lvl,
+                                               const Sink& out, uint32_t* scr, int wave, int lane) {
+    const uint32_t* pw = mt.plan + 2u * (lvl * 16u + (uint32_t)wave);
+    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)pw[0]);
+    uint32_t own = (uint32_t)__builtin_amdgcn_readfirstlane((int)pw[1]);
+    auto run = [&](uint32_t i, uint32_t d0, uint32_t d1, bool whole) {
+        const uint32_t g0 = min((2u * i) << lvl, nseg0);
+        const uint32_t g1 = min((2u * i + 1u) << lvl, nseg0);
+        const uint32_t g2 = min((2u * i + 2u) << lvl, nseg0);
+        const uint32_t aA = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.sbeg[g0]);
+        const uint32_t aB = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.sbeg[g1]);
+        const uint32_t p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.plen[g0]);
+        const uint32_t p1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.plen[g1]);
+        const uint32_t p2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.plen[g2]);
+        const uint32_t la = p1 - p0, lb = p2 - p1;
+        if (whole) d1 = la + lb;
+        if (d0 < d1) merge_pair_range_kt<EM>(X, aA, la, aB, lb, d0, d1, out, aA, scr, lane);
+    };
+    run(w0 & 15u, (w0 >> 4) & 0x3FFFu, w0 >> 18, false);
+    while (own) {
+        const uint32_t i = (uint32_t)__builtin_ctz(own);
+        own &= own - 1u;
+        run(i, 0u, 0u, true);
     }
 }
 

@@ -176,7 +176,7 @@ hipError_t launch_copy(const uint32_t* in, uint32_t* out, uint64_t n, hipStream_
 // compute unit).
 constexpr uint32_t kT64Keys = 4096;
 constexpr uint32_t kT64Pairs = 2048;
-constexpr uint32_t kTout64Keys = 4096;
+constexpr uint32_t kTout64Keys = 3840;
 constexpr uint32_t kTout64Pairs = 2048;
 
 struct Bufs64 {

@@ -21,6 +21,8 @@
 #include "mms_corank.h"
 #include "mms_device.h"
 #include "mms_device64.h"
+#include "mms_device_kt.h"
+#include "mms_tile_plan.h"
 #include "mms_internal.h"
 
 namespace mms {
@@ -286,6 +288,103 @@ __global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundA
 }
 
 // ===========================================================================
+// Keys-only K-way merge of one output tile (§4.2, §7) with the transposed
+// block step of the 32-bit merges on 64-bit words: every wave lays the
+// tile's pieces out at 4-aligned slots from the split rows and issues its
+// LDS copies at once, wave 0 plans each level's work per wave, and the
+// levels merge 64x8-key blocks sorted in registers through two transposes
+// of the words' halves.  LDS: two level buffers of cap = Tout + 4K keys, the
+// waves' transpose scratch, the piece table and plan (two workgroups per CU
+// at 3840-key tiles).
+// ===========================================================================
+constexpr uint32_t kMetaWords64 = 3u * 17u + kPlanWords;
+
+template <int W>
+__global__ __launch_bounds__(W * 64, 4) void k_merge64_keys(Phase64 ph, Bufs64 b, RoundArgs ra,
+                                                            const uint32_t* __restrict__ table, uint64_t flip) {
+    constexpr int EM = 8;
+    const uint32_t Tout = ra.Tout, K = ra.K;
+    const uint64_t L = ra.L;
+    const uint32_t cap = Tout + 4u * K;
+    extern __shared__ __align__(16) uint64_t smem64[];
+    uint64_t* X = smem64;
+    uint64_t* Y = smem64 + cap;
+    uint32_t* scr = reinterpret_cast<uint32_t*>(Y + cap);
+    uint32_t* mb = scr + W * Xpose<EM>::WORDS;
+    const Meta mt{mb, mb + 17, mb + 34, mb + 51, nullptr};
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    uint32_t* wscr = scr + (uint32_t)wave * Xpose<EM>::WORDS;
+    const uint64_t t = blockIdx.x;
+    const uint64_t* src = ph.dst_out ? b.ws_k : b.out_k;
+    uint64_t* dst = ph.dst_out ? b.out_k : b.ws_k;
+    const uint64_t flip_out = ph.final_pass ? flip : 0ull;
+    const uint64_t grp = t / ra.tpg;
+    const uint64_t i = t - grp * ra.tpg;
+    const uint64_t span = (uint64_t)K * L;
+    const uint64_t gb = grp * span;
+    const uint64_t glen = min(span, ph.n - gb);
+    const uint32_t Kg = (uint32_t)((glen + L - 1) / L);
+    const uint64_t obeg = i * (uint64_t)Tout;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(Tout, glen - obeg);
+    const uint64_t obase = gb + obeg;
+
+    if (Kg == 1) {   // a lone run: its tile is already in order
+        for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) gptr64(dst)[obase + j] = gptr64(src)[obase + j] ^ flip_out;
+        return;
+    }
+    uint32_t s = 0, e = 0;
+    if ((uint32_t)lane < Kg) {
+        const uint32_t k = (uint32_t)lane;
+        const uint32_t nk = (uint32_t)min(L, glen - (uint64_t)k * L);
+        // the clamps only guard memory safety; exact splits never trigger them
+        s = i == 0 ? 0u : min(table[t * K + k], nk);
+        e = (obeg + Tout >= glen) ? nk : min(max(table[(t + 1) * K + k], s), nk);
+    }
+    {
+        // each piece's keys (two words each) go into LDS by the memory unit,
+        // 64 words per instruction, chunks dealt to the waves round-robin
+        const PieceLayout pc = piece_layout(s, e, Kg, cnt, lane);
+        const uint32_t* src32 = reinterpret_cast<const uint32_t*>(src);
+        uint32_t* X32 = reinterpret_cast<uint32_t*>(X);
+        uint32_t cbase = 0;
+        for (uint32_t k = 0; k < Kg; ++k) {
+            const uint32_t w0 = 2u * (uint32_t)__builtin_amdgcn_readlane((int)pc.sb, (int)k);
+            const uint32_t nw = 2u * (uint32_t)__builtin_amdgcn_readlane((int)pc.len, (int)k);
+            const uint32_t st = (uint32_t)__builtin_amdgcn_readlane((int)s, (int)k);
+            const uint32_t nch = (nw + 63u) >> 6;
+            const uint64_t run0 = 2u * (gb + (uint64_t)k * L + st);   // the piece's first word
+            for (uint32_t c = ((uint32_t)wave + W - cbase % W) % W; c < nch; c += W) {
+                if (64u * c + (uint32_t)lane < nw) dma_dword(src32 + run0 + 64u * c, (uint32_t)lane, X32 + w0 + 64u * c);
+            }
+            cbase += nch;
+        }
+    }
+    if (wave == 0) {   // the other waves wait for this plan: it issues first
+        __builtin_amdgcn_s_setprio(2);
+        build_pieces(mt, s, e, Kg, cnt, lane);
+        lds_wave_sync();
+        build_plan<W>(mt, Kg, lane);
+        __builtin_amdgcn_s_setprio(0);
+    }
+    vm_drain();
+    lds_barrier();
+
+    uint32_t nlev = 0;
+    while ((1u << nlev) < Kg) ++nlev;
+    const bool vec = ((uintptr_t)(dst + obase) & 15u) == 0;
+    const U64SinkGlobal gout{dst + obase, flip_out, cnt, vec};
+    for (uint32_t lvl = 0; lvl < nlev; ++lvl) {
+        const U64Src in{X};
+        if (lvl + 1u == nlev) merge_level_kt<EM>(in, mt, Kg, lvl, gout, wscr, wave, lane);
+        else merge_level_kt<EM>(in, mt, Kg, lvl, U64SinkLds{Y}, wscr, wave, lane);
+        lds_barrier();
+        uint64_t* tmp = X; X = Y; Y = tmp;
+    }
+}
+
+// ===========================================================================
 // Launchers
 // ===========================================================================
 static hipError_t allow_lds64(const void* f, size_t bytes) {
@@ -323,17 +422,21 @@ hipError_t launch_corank_tiles64(const Phase64& ph, const Bufs64& b, const Round
 hipError_t launch_merge64(bool pairs, const Phase64& ph, const Bufs64& b, const RoundArgs& ra, const uint32_t* table,
                           uint64_t flip, hipStream_t s) {
     if (ph.tiles == 0) return hipSuccess;
-    if (ra.K > kMaxFanout || ra.Tout > (pairs ? kTout64Pairs : kTout64Keys)) return hipErrorInvalidValue;
+    if (ra.K > kMaxFanout || ra.Tout > (pairs ? kTout64Pairs : kTout64Keys) || ra.Tout % 4) return hipErrorInvalidValue;
     constexpr int W = 8;
+    if (!pairs) {
+        const uint32_t cap = ra.Tout + 4u * ra.K;
+        const size_t lds = 8u * 2u * cap + (W * Xpose<8>::WORDS + kMetaWords64) * sizeof(uint32_t);
+        hipError_t e = allow_lds64((const void*)k_merge64_keys<W>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_merge64_keys<W>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, ra, table, flip);
+        return hipGetLastError();
+    }
     // keys 2 x Tout; pairs: values Tout and 16-bit tags 2 x Tout more
-    const size_t lds = (pairs ? 28u : 16u) * ra.Tout + (2u * kMaxFanout + 4u) * sizeof(uint32_t);
-    const void* f = pairs ? (const void*)k_merge64<W, true> : (const void*)k_merge64<W, false>;
-    hipError_t e = allow_lds64(f, lds);
+    const size_t lds = 28u * ra.Tout + (2u * kMaxFanout + 4u) * sizeof(uint32_t);
+    hipError_t e = allow_lds64((const void*)k_merge64<W, true>, lds);
     if (e != hipSuccess) return e;
-    if (pairs)
-        hipLaunchKernelGGL((k_merge64<W, true>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, ra, table, flip);
-    else
-        hipLaunchKernelGGL((k_merge64<W, false>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, ra, table, flip);
+    hipLaunchKernelGGL((k_merge64<W, true>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, ra, table, flip);
     return hipGetLastError();
 }
 

@@ -27,34 +27,6 @@ namespace {
 constexpr int kEMP = 8;   // 64 x 8-pair merge blocks
 constexpr uint32_t kMetaWordsP = 3u * 17u + kPlanWords;
 
-// One planned merge level (the plan's encoding as in the keys merge).
-template <class Src, class Sink>
-__device__ __forceinline__ void merge_level_kt(const Src& X, const Meta& mt, uint32_t nseg0, uint32_t lvl,
-                                               const Sink& out, uint32_t* scr, int wave, int lane) {
-    const uint32_t* pw = mt.plan + 2u * (lvl * 16u + (uint32_t)wave);
-    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)pw[0]);
-    uint32_t own = (uint32_t)__builtin_amdgcn_readfirstlane((int)pw[1]);
-    auto run = [&](uint32_t i, uint32_t d0, uint32_t d1, bool whole) {
-        const uint32_t g0 = min((2u * i) << lvl, nseg0);
-        const uint32_t g1 = min((2u * i + 1u) << lvl, nseg0);
-        const uint32_t g2 = min((2u * i + 2u) << lvl, nseg0);
-        const uint32_t aA = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.sbeg[g0]);
-        const uint32_t aB = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.sbeg[g1]);
-        const uint32_t p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.plen[g0]);
-        const uint32_t p1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.plen[g1]);
-        const uint32_t p2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)mt.plen[g2]);
-        const uint32_t la = p1 - p0, lb = p2 - p1;
-        if (whole) d1 = la + lb;
-        if (d0 < d1) merge_pair_range_kt<kEMP>(X, aA, la, aB, lb, d0, d1, out, aA, scr, lane);
-    };
-    run(w0 & 15u, (w0 >> 4) & 0x3FFFu, w0 >> 18, false);
-    while (own) {
-        const uint32_t i = (uint32_t)__builtin_ctz(own);
-        own &= own - 1u;
-        run(i, 0u, 0u, true);
-    }
-}
-
 }  // namespace
 
 template <int W>
@@ -146,16 +118,17 @@ __global__ __launch_bounds__(W * 64, 4) void k_merge_pairs(Phase ph, Bufs b, Rou
     uint32_t* Yk = K1;
     uint16_t* Yt = T1;
     const bool vec = (((uintptr_t)(tr.dst_k + obase) | (uintptr_t)(tr.dst_v + obase)) & 15u) == 0;
+    const KtSinkGlobal gout{tr.dst_k + obase, tr.dst_v + obase, V, flip_out, cnt, vec};
     for (uint32_t lvl = 0; lvl < nlev; ++lvl) {
         const bool last = lvl + 1u == nlev;
         if (lvl == 0) {
             const KtSrcLoaded X{Xk};
-            if (last) merge_level_kt(X, mt, Kg, lvl, KtSinkGlobal{tr.dst_k + obase, tr.dst_v + obase, V, flip_out, cnt, vec}, wscr, wave, lane);
-            else merge_level_kt(X, mt, Kg, lvl, KtSinkLds{Yk, Yt}, wscr, wave, lane);
+            if (last) merge_level_kt<kEMP>(X, mt, Kg, lvl, gout, wscr, wave, lane);
+            else merge_level_kt<kEMP>(X, mt, Kg, lvl, KtSinkLds{Yk, Yt}, wscr, wave, lane);
         } else {
             const KtSrcTagged X{Xk, Xt};
-            if (last) merge_level_kt(X, mt, Kg, lvl, KtSinkGlobal{tr.dst_k + obase, tr.dst_v + obase, V, flip_out, cnt, vec}, wscr, wave, lane);
-            else merge_level_kt(X, mt, Kg, lvl, KtSinkLds{Yk, Yt}, wscr, wave, lane);
+            if (last) merge_level_kt<kEMP>(X, mt, Kg, lvl, gout, wscr, wave, lane);
+            else merge_level_kt<kEMP>(X, mt, Kg, lvl, KtSinkLds{Yk, Yt}, wscr, wave, lane);
         }
         lds_barrier();
         uint32_t* tk = Xk; Xk = Yk; Yk = tk;
