@@ -350,8 +350,10 @@ def measure(mms, torch, np, x_host, *, pairs: bool, i32: bool, steps: int, warmu
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    # the timed steps: HIP events bracket the merge launches only (each timed
+    # launch costs two event records on the stream), for the roofline figure
     mms.timing_reset()
-    mms.timing_enable(True)
+    mms.timing_enable(True, kinds=["merge"])
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -361,8 +363,17 @@ def measure(mms, torch, np, x_host, *, pairs: bool, i32: bool, steps: int, warmu
     stop.record(stream)
     torch.cuda.synchronize()
     mms.timing_enable(False)
-    times = mms.timing_read()
+    timed = mms.timing_read()
     ms_per_step = start.elapsed_time(stop) / steps
+    # the per-phase breakdown from a few more steps with every launch timed
+    b_steps = max(1, min(steps, 5))
+    mms.timing_reset()
+    mms.timing_enable(True)
+    for _ in range(b_steps):
+        step()
+    torch.cuda.synchronize()
+    mms.timing_enable(False)
+    times = mms.timing_read()
 
     if wide:
         o = out if i32 else out ^ (-(2**63))      # unsigned order as signed order
@@ -380,11 +391,12 @@ def measure(mms, torch, np, x_host, *, pairs: bool, i32: bool, steps: int, warmu
         raise RuntimeError("bench.py: output is not sorted")
     s_bytes = (8 if wide else 4) * (2 if pairs else 1)
     alg_bytes = 2 * s_bytes * n        # one read and one write of every element per launch
-    phases = {k: {"launches": c, "ms_per_step": round(t / steps, 4)} for k, (c, t) in times.items() if c}
+    phases = {k: {"launches_per_step": c // b_steps, "ms_per_step": round(t / b_steps, 4)}
+              for k, (c, t) in times.items() if c}
     dom = max((k for k in ("tile_sort", "partition", "merge") if times[k][0]), key=lambda k: times[k][1])
-    m_launches, m_ms = times["merge"]
+    m_launches, m_ms = timed["merge"]                  # launches of the timed steps
     merge_avg_ms = m_ms / max(1, m_launches)
-    d_launches, d_ms = times[dom]
+    d_launches, d_ms = timed[dom] if timed[dom][0] else times[dom]
     dom_avg = d_ms / max(1, d_launches)
     plan = mms.plan(n, pairs=pairs, i32=i32 and not wide, keys64=wide, mergepath=kind == "mergepath")
     del x, out, v, vout, ws

@@ -369,11 +369,14 @@ int mms_server_destroy(mms_server* s);
 
 /*
  * Per-kernel timing, for measurement harnesses.  While enabled, every kernel
- * the library launches is bracketed by two hipEvents recorded on the stream
- * it is launched on, and mms_timing_read() waits for those events and
- * returns, per kernel kind, the number of launches and their summed
- * durations since the last reset.  Enabling costs two event records per
- * launch.  The state is process-wide; calls are thread-safe.
+ * of a selected kind the library launches is bracketed by two hipEvents
+ * recorded on the stream it is launched on, and mms_timing_read() waits for
+ * those events and returns, per kernel kind, the number of launches and
+ * their summed durations since the last reset.  Each timed launch costs two
+ * event records (a few microseconds of stream time).  mms_timing_kinds()
+ * selects the kinds (bit k for kind k; all kinds until it is called; a mask
+ * with no known kind is rejected with MMS_EINVAL).  The state is
+ * process-wide; calls are thread-safe.
  */
 typedef enum {
     MMS_KERNEL_TILE_SORT = 0,  /* base case (§4.3)          */
@@ -390,6 +393,7 @@ typedef struct {
 } mms_timing_t;
 
 int mms_timing_enable(int on);
+int mms_timing_kinds(uint32_t mask);
 int mms_timing_reset(void);
 int mms_timing_read(mms_timing_t* out);
 

@@ -212,8 +212,16 @@ def copy(src, dst, stream=None):
     return dst
 
 
-def timing_enable(on: bool = True):
-    """Bracket every library kernel launch with HIP events on its stream."""
+def timing_enable(on: bool = True, kinds=None):
+    """Bracket library kernel launches with HIP events on their streams: all
+    kinds, or those named in `kinds` (names of timing_read's keys)."""
+    if kinds is not None:
+        mask = 0
+        for k in kinds:
+            mask |= 1 << _lib.KERNEL_KINDS.index(k)
+        _lib.check(_lib.lib().mms_timing_kinds(mask))
+    elif on:
+        _lib.check(_lib.lib().mms_timing_kinds((1 << len(_lib.KERNEL_KINDS)) - 1))
     _lib.check(_lib.lib().mms_timing_enable(1 if on else 0))
 
 

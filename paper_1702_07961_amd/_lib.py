@@ -35,7 +35,7 @@ MMS_MERGEPATH = 0x10
 # every symbol include/mms.h declares
 EXPORTS = [
     "mms_last_error", "mms_version", "mms_plan", "mms_workspace_bytes", "mms_sort_u32",
-    "mms_sort_pairs_u32", "mms_sort_u64", "mms_sort_pairs_u64", "mms_sort_mergepath_u32", "mms_sort_u32_noalloc", "mms_partition_u32", "mms_copy_u32", "mms_timing_enable",
+    "mms_sort_pairs_u32", "mms_sort_u64", "mms_sort_pairs_u64", "mms_sort_mergepath_u32", "mms_sort_u32_noalloc", "mms_partition_u32", "mms_copy_u32", "mms_timing_enable", "mms_timing_kinds",
     "mms_timing_reset", "mms_timing_read", "mms_segmented_workspace_bytes", "mms_segmented_sort",
     "mms_set_tuning", "mms_get_tuning", "mms_server_create", "mms_submit", "mms_poll", "mms_wait",
     "mms_release", "mms_server_get_stats", "mms_server_destroy",
@@ -167,6 +167,8 @@ def _declare(lib):
     lib.mms_copy_u32.restype = ctypes.c_int
     lib.mms_timing_enable.argtypes = [ctypes.c_int]
     lib.mms_timing_enable.restype = ctypes.c_int
+    lib.mms_timing_kinds.argtypes = [ctypes.c_uint32]
+    lib.mms_timing_kinds.restype = ctypes.c_int
     lib.mms_timing_reset.argtypes = []
     lib.mms_timing_reset.restype = ctypes.c_int
     lib.mms_timing_read.argtypes = [ctypes.POINTER(MmsTiming)]

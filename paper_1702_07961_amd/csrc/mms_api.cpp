@@ -49,6 +49,7 @@ struct TimingRec {
 };
 std::mutex g_tmu;
 bool g_timing = false;
+uint32_t g_kinds = (1u << MMS_KERNEL_KINDS) - 1u;   // kinds that are timed
 std::vector<TimingRec> g_recs;
 std::vector<hipEvent_t> g_pool;
 uint64_t g_launch[MMS_KERNEL_KINDS];
@@ -72,7 +73,7 @@ void set_capturing(bool on) { g_capturing = on; }
 Timed::Timed(int kind, hipStream_t s) : kind_(kind), s_(s) {
     if (g_capturing) return;
     std::lock_guard<std::mutex> g(g_tmu);
-    if (!g_timing) return;
+    if (!g_timing || !((g_kinds >> kind) & 1u)) return;
     a_ = take_event();
     b_ = take_event();
     if (a_ && b_) (void)hipEventRecord(a_, s_);
@@ -897,6 +898,14 @@ int mms_copy_u32(const uint32_t* d_in, uint32_t* d_out, uint64_t n, void* stream
 int mms_timing_enable(int on) {
     std::lock_guard<std::mutex> g(g_tmu);
     g_timing = on != 0;
+    return MMS_OK;
+}
+
+int mms_timing_kinds(uint32_t mask) {
+    const uint32_t all = (1u << MMS_KERNEL_KINDS) - 1u;
+    if (!(mask & all) || (mask & ~all)) return fail(MMS_EINVAL, "timing kinds mask 0x%x selects no known kind", mask);
+    std::lock_guard<std::mutex> g(g_tmu);
+    g_kinds = mask;
     return MMS_OK;
 }
 

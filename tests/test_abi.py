@@ -148,6 +148,17 @@ def test_copy_argument_errors(lib):
     assert lib.mms_copy_u32(FAKE, FAKE, 0, None) == _lib.MMS_OK
 
 
+def test_timing_kinds(lib):
+    """The timed kernel kinds are a bit mask over the known kinds; a mask that
+    selects none of them is an argument error."""
+    all_kinds = (1 << len(_lib.KERNEL_KINDS)) - 1
+    assert lib.mms_timing_kinds(0) == _lib.MMS_EINVAL
+    assert lib.mms_timing_kinds(1 << len(_lib.KERNEL_KINDS)) == _lib.MMS_EINVAL
+    assert lib.mms_timing_kinds(all_kinds | (1 << 31)) == _lib.MMS_EINVAL
+    assert lib.mms_timing_kinds(1 << _lib.KERNEL_KINDS.index("merge")) == _lib.MMS_OK
+    assert lib.mms_timing_kinds(all_kinds) == _lib.MMS_OK
+
+
 def test_last_error_is_per_thread(lib):
     import threading
     lib.mms_plan(1 << 33, 0, _lib.MmsPlan())
