@@ -6,9 +6,11 @@
 //                 (a bitonic network per wave, then bitonic merges across
 //                 the waves through LDS)
 //   corank64      partition (§4.1): the exact split of each output tile
-//   merge64       K-way merge of one output tile through LDS (§4.2, §7):
-//                 the pieces are loaded back to back and merged pairwise in
-//                 log2 K levels of conflict-free block merges
+//   merge64       K-way merge of one output tile through LDS (§4.2, §7),
+//                 log2 K levels of pairwise block merges: keys with the
+//                 transposed block step of the 32-bit merges on 64-bit words
+//                 (pieces at 4-aligned slots, a per-wave level plan), pairs
+//                 with lane-exchange networks on (key, tag) elements
 //
 // Pairs carry (key, tag) through every network, the tag being the element's
 // slot in the tile as loaded, so every step is stable; the values stay in LDS
