@@ -438,6 +438,30 @@ __device__ __forceinline__ void block_sort_keys(uint32_t (&m)[EM], uint32_t* scr
     }
 }
 
+// Store a block held in layout F: chunk c of lane l is block positions
+// p = c*256 + 4l .. p+3.  put4(c, p) stores a whole chunk, put1(c, j, p + j)
+// one position; positions at or past lim are not stored, and whole chunks
+// only where vec allows it.  A whole block takes one wave-uniform branch.
+template <int EM, class Put4, class Put1>
+__device__ __forceinline__ void store_block(uint32_t lim, bool vec, int lane, const Put4& put4, const Put1& put1) {
+    if (vec && lim >= (uint32_t)EM * 64u) {
+#pragma unroll
+        for (int c = 0; c < EM / 4; ++c) put4(c, (uint32_t)c * 256u + 4u * (uint32_t)lane);
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < EM / 4; ++c) {
+        const uint32_t p = (uint32_t)c * 256u + 4u * (uint32_t)lane;
+        if (vec && p + 4u <= lim) {
+            put4(c, p);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (p + (uint32_t)j < lim) put1(c, j, p + (uint32_t)j);
+        }
+    }
+}
+
 // Sinks for a sorted block in layout F: block position t = c*256 + 4*lane + j
 // goes to pos0 + t when t < cnt.  pos0 must be a multiple of 4 for the
 // 16-byte path; `vec` says whether the base pointer allows it.
@@ -445,17 +469,13 @@ struct LdsSinkKeys {
     uint32_t* y;
     template <int EM>
     __device__ __forceinline__ void put_block(uint32_t pos0, uint32_t cnt, const uint32_t (&m)[EM], int lane) const {
-#pragma unroll
-        for (int c = 0; c < EM / 4; ++c) {
-            const uint32_t t = (uint32_t)c * 256u + 4u * (uint32_t)lane;
-            if (t + 4u <= cnt) {
-                *reinterpret_cast<uint4*>(y + pos0 + t) = make_uint4(m[4 * c], m[4 * c + 1], m[4 * c + 2], m[4 * c + 3]);
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (t + (uint32_t)j < cnt) y[pos0 + t + j] = m[4 * c + j];
-            }
-        }
+        uint32_t* o = y + pos0;
+        store_block<EM>(
+            cnt, true, lane,
+            [&](int c, uint32_t p) {
+                *reinterpret_cast<uint4*>(o + p) = make_uint4(m[4 * c], m[4 * c + 1], m[4 * c + 2], m[4 * c + 3]);
+            },
+            [&](int c, int j, uint32_t p) { o[p] = m[4 * c + j]; });
     }
 };
 struct GlobalSinkKeys {
@@ -465,37 +485,26 @@ struct GlobalSinkKeys {
     bool vec;        // y is 16-byte aligned
     template <int EM>
     __device__ __forceinline__ void put_block(uint32_t pos0, uint32_t cnt, const uint32_t (&m)[EM], int lane) const {
-        const uint32_t c_lim = min(cnt, lim > pos0 ? lim - pos0 : 0u);
-        gu32* g = gptr(y);
-#pragma unroll
-        for (int c = 0; c < EM / 4; ++c) {
-            const uint32_t t = (uint32_t)c * 256u + 4u * (uint32_t)lane;
-            if (vec && t + 4u <= c_lim) {
-                *reinterpret_cast<gu32x4*>(g + pos0 + t) =
+        gu32* g = gptr(y) + pos0;
+        store_block<EM>(
+            min(cnt, lim > pos0 ? lim - pos0 : 0u), vec, lane,
+            [&](int c, uint32_t p) {
+                *reinterpret_cast<gu32x4*>(g + p) =
                     u32x4{m[4 * c] ^ flip, m[4 * c + 1] ^ flip, m[4 * c + 2] ^ flip, m[4 * c + 3] ^ flip};
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (t + (uint32_t)j < c_lim) g[pos0 + t + j] = m[4 * c + j] ^ flip;
-            }
-        }
+            },
+            [&](int c, int j, uint32_t p) { g[p] = m[4 * c + j] ^ flip; });
     }
 };
 
-// Number of block positions k = 64 e + lane with a_k <= b_k.  a is
-// non-decreasing and b non-increasing in k, so those positions are a prefix
-// of the block: a binary search over the registers, testing each one's last
-// lane, finds the register the prefix ends in (log2 EM + 1 ballots instead of
-// EM).  Registers below LO are known to hold only positions of the prefix.
-template <int LO, int HI, int EM>
+// Number of block positions k = 64 e + lane with a_k <= b_k: the sum of the
+// registers' ballot counts, with no branch (a is non-decreasing and b
+// non-increasing in k, so the positions form a prefix of the block).
+template <int EM>
 __device__ __forceinline__ uint32_t prefix_len(const uint32_t (&a)[EM], const uint32_t (&b)[EM]) {
-    if constexpr (HI - LO == 1) {
-        return (uint32_t)LO * 64u + (uint32_t)__popcll(__ballot(a[LO] <= b[LO]));
-    } else {
-        constexpr int MID = (LO + HI) / 2;
-        if (__ballot(a[MID - 1] <= b[MID - 1]) >> 63) return prefix_len<MID, HI, EM>(a, b);
-        return prefix_len<LO, MID, EM>(a, b);
-    }
+    uint32_t u = 0;
+#pragma unroll
+    for (int e = 0; e < EM; ++e) u += (uint32_t)__popcll(__ballot(a[e] <= b[e]));
+    return u;
 }
 
 // Merge outputs [d0, d1) of A = X[aA, aA+la) and B = X[aB, aB+lb) (keys),
@@ -542,7 +551,7 @@ __device__ __forceinline__ void merge_pair_range_keys(const uint32_t* X, uint32_
             }
 #pragma unroll
             for (int e = 0; e < EM; ++e) m[e] = min(a[e], b[e]);
-            u = prefix_len<0, EM, EM>(a, b);
+            u = prefix_len<EM>(a, b);
         } else {
             // near the end of a run: the same reads, then the sentinel for
             // every position past the run's end, with no branch per element.
@@ -568,7 +577,7 @@ __device__ __forceinline__ void merge_pair_range_keys(const uint32_t* X, uint32_
                 b[e] = N - 1u - k < rb ? b[e] : kSentKey;  // still non-increasing in k
                 m[e] = min(a[e], b[e]);
             }
-            u = prefix_len<0, EM, EM>(a, b);
+            u = prefix_len<EM>(a, b);
         }
         block_sort_keys<EM>(m, scr, lane);
         out.template put_block<EM>(out_base + o, min(N, d1 - o), m, lane);

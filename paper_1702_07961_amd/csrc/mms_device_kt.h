@@ -194,17 +194,14 @@ __device__ __forceinline__ ElemKT shfl_xor(const ElemKT& e, int m) {
 }
 
 // Number of block positions k with a_k < b_k (a increasing and b
-// decreasing in k, so they form a prefix): a binary search over the
-// registers' last lanes, as prefix_len does for keys.
-template <int LO, int HI, int EM, class T>
+// decreasing in k, so they form a prefix): the sum of the registers' ballot
+// counts, with no branch, as prefix_len does for keys.
+template <int EM, class T>
 __device__ __forceinline__ uint32_t prefix_len_kt(const T (&a)[EM], const T (&b)[EM]) {
-    if constexpr (HI - LO == 1) {
-        return (uint32_t)LO * 64u + (uint32_t)__popcll(__ballot(a[LO] < b[LO]));
-    } else {
-        constexpr int MID = (LO + HI) / 2;
-        if (__ballot(a[MID - 1] < b[MID - 1]) >> 63) return prefix_len_kt<MID, HI, EM, T>(a, b);
-        return prefix_len_kt<LO, MID, EM, T>(a, b);
-    }
+    uint32_t u = 0;
+#pragma unroll
+    for (int e = 0; e < EM; ++e) u += (uint32_t)__popcll(__ballot(a[e] < b[e]));
+    return u;
 }
 
 // LDS sources of a merge level.  Level 0 reads the keys as loaded, each
@@ -272,26 +269,22 @@ struct KtSinkLds {
     uint16_t* t;
     template <int EM>
     __device__ __forceinline__ void put_block(uint32_t pos0, uint32_t cnt, const double (&m)[EM], int lane) const {
-#pragma unroll
-        for (int c = 0; c < EM / 4; ++c) {
-            const uint32_t p = (uint32_t)c * 256u + 4u * (uint32_t)lane;
-            const double* r = m + 4 * c;
-            if (p + 4u <= cnt) {
-                *reinterpret_cast<uint4*>(k + pos0 + p) = make_uint4(kt_key(r[0]), kt_key(r[1]), kt_key(r[2]), kt_key(r[3]));
+        uint32_t* ok = k + pos0;
+        uint16_t* ot = t + pos0;
+        store_block<EM>(
+            cnt, true, lane,
+            [&](int c, uint32_t p) {
+                const double* r = m + 4 * c;
+                *reinterpret_cast<uint4*>(ok + p) = make_uint4(kt_key(r[0]), kt_key(r[1]), kt_key(r[2]), kt_key(r[3]));
                 // two 16-bit tags per word: the low halves of the low words
-                *reinterpret_cast<uint2*>(t + pos0 + p) =
+                *reinterpret_cast<uint2*>(ot + p) =
                     make_uint2(__builtin_amdgcn_perm(kt_lo(r[1]), kt_lo(r[0]), 0x05040100u),
                                __builtin_amdgcn_perm(kt_lo(r[3]), kt_lo(r[2]), 0x05040100u));
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (p + (uint32_t)j < cnt) {
-                        k[pos0 + p + j] = kt_key(r[j]);
-                        t[pos0 + p + j] = (uint16_t)kt_lo(r[j]);
-                    }
-                }
-            }
-        }
+            },
+            [&](int c, int j, uint32_t p) {
+                ok[p] = kt_key(m[4 * c + j]);
+                ot[p] = (uint16_t)kt_lo(m[4 * c + j]);
+            });
     }
 };
 // The last level: keys to memory (undoing the signed-key mapping) and each
@@ -305,28 +298,21 @@ struct KtSinkGlobal {
     bool vec;            // k and v are 16-byte aligned
     template <int EM>
     __device__ __forceinline__ void put_block(uint32_t pos0, uint32_t cnt, const double (&m)[EM], int lane) const {
-        const uint32_t c_lim = min(cnt, lim > pos0 ? lim - pos0 : 0u);
-        gu32* gk = gptr(k);
-        gu32* gv = gptr(v);
-#pragma unroll
-        for (int c = 0; c < EM / 4; ++c) {
-            const uint32_t p = (uint32_t)c * 256u + 4u * (uint32_t)lane;
-            const double* r = m + 4 * c;
-            if (vec && p + 4u <= c_lim) {
-                *reinterpret_cast<gu32x4*>(gk + pos0 + p) =
+        gu32* gk = gptr(k) + pos0;
+        gu32* gv = gptr(v) + pos0;
+        store_block<EM>(
+            min(cnt, lim > pos0 ? lim - pos0 : 0u), vec, lane,
+            [&](int c, uint32_t p) {
+                const double* r = m + 4 * c;
+                *reinterpret_cast<gu32x4*>(gk + p) =
                     u32x4{kt_key(r[0]) ^ flip, kt_key(r[1]) ^ flip, kt_key(r[2]) ^ flip, kt_key(r[3]) ^ flip};
-                *reinterpret_cast<gu32x4*>(gv + pos0 + p) =
+                *reinterpret_cast<gu32x4*>(gv + p) =
                     u32x4{V[kt_tag(r[0])], V[kt_tag(r[1])], V[kt_tag(r[2])], V[kt_tag(r[3])]};
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (p + (uint32_t)j < c_lim) {
-                        gk[pos0 + p + j] = kt_key(r[j]) ^ flip;
-                        gv[pos0 + p + j] = V[kt_tag(r[j])];
-                    }
-                }
-            }
-        }
+            },
+            [&](int c, int j, uint32_t p) {
+                gk[p] = kt_key(m[4 * c + j]) ^ flip;
+                gv[p] = V[kt_tag(m[4 * c + j])];
+            });
     }
 };
 
@@ -386,7 +372,7 @@ __device__ __forceinline__ void merge_pair_range_kt(const Src& X, uint32_t aA, u
             read_block<EM>(A, B, a, b);
 #pragma unroll
             for (int e = 0; e < EM; ++e) m[e] = w_min(a[e], b[e]);
-            u = prefix_len_kt<0, EM, EM, T>(a, b);
+            u = prefix_len_kt<EM, T>(a, b);
         } else {
             // near the end of a run: the same reads, then the sentinel for
             // every position past a run's end.  Those reads stay below the
@@ -408,7 +394,7 @@ __device__ __forceinline__ void merge_pair_range_kt(const Src& X, uint32_t aA, u
                 b[e] = N - 1u - k < rb ? b[e] : w_sentinel<T>();
                 m[e] = w_min(a[e], b[e]);
             }
-            u = prefix_len_kt<0, EM, EM, T>(a, b);
+            u = prefix_len_kt<EM, T>(a, b);
         }
         block_sort_kt<EM>(m, scr, lane);
         out.template put_block<EM>(out_base + o, min(N, d1 - o), m, lane);
@@ -454,19 +440,15 @@ struct U64SinkLds {
     uint64_t* k;
     template <int EM>
     __device__ __forceinline__ void put_block(uint32_t pos0, uint32_t cnt, const uint64_t (&m)[EM], int lane) const {
-#pragma unroll
-        for (int c = 0; c < EM / 4; ++c) {
-            const uint32_t p = (uint32_t)c * 256u + 4u * (uint32_t)lane;
-            const uint64_t* r = m + 4 * c;
-            if (p + 4u <= cnt) {
-                *reinterpret_cast<ulonglong2*>(k + pos0 + p) = make_ulonglong2(r[0], r[1]);
-                *reinterpret_cast<ulonglong2*>(k + pos0 + p + 2) = make_ulonglong2(r[2], r[3]);
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (p + (uint32_t)j < cnt) k[pos0 + p + j] = r[j];
-            }
-        }
+        uint64_t* o = k + pos0;
+        store_block<EM>(
+            cnt, true, lane,
+            [&](int c, uint32_t p) {
+                const uint64_t* r = m + 4 * c;
+                *reinterpret_cast<ulonglong2*>(o + p) = make_ulonglong2(r[0], r[1]);
+                *reinterpret_cast<ulonglong2*>(o + p + 2) = make_ulonglong2(r[2], r[3]);
+            },
+            [&](int c, int j, uint32_t p) { o[p] = m[4 * c + j]; });
     }
 };
 struct U64SinkGlobal {
@@ -479,21 +461,15 @@ struct U64SinkGlobal {
         typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
         typedef __attribute__((address_space(1))) u64x2 gu64x2_t;
         typedef __attribute__((address_space(1))) uint64_t gu64_t;
-        const uint32_t c_lim = min(cnt, lim > pos0 ? lim - pos0 : 0u);
-        gu64_t* g = (gu64_t*)k;
-#pragma unroll
-        for (int c = 0; c < EM / 4; ++c) {
-            const uint32_t p = (uint32_t)c * 256u + 4u * (uint32_t)lane;
-            const uint64_t* r = m + 4 * c;
-            if (vec && p + 4u <= c_lim) {
-                *reinterpret_cast<gu64x2_t*>(g + pos0 + p) = u64x2{r[0] ^ flip, r[1] ^ flip};
-                *reinterpret_cast<gu64x2_t*>(g + pos0 + p + 2) = u64x2{r[2] ^ flip, r[3] ^ flip};
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (p + (uint32_t)j < c_lim) g[pos0 + p + j] = r[j] ^ flip;
-            }
-        }
+        gu64_t* g = (gu64_t*)k + pos0;
+        store_block<EM>(
+            min(cnt, lim > pos0 ? lim - pos0 : 0u), vec, lane,
+            [&](int c, uint32_t p) {
+                const uint64_t* r = m + 4 * c;
+                *reinterpret_cast<gu64x2_t*>(g + p) = u64x2{r[0] ^ flip, r[1] ^ flip};
+                *reinterpret_cast<gu64x2_t*>(g + p + 2) = u64x2{r[2] ^ flip, r[3] ^ flip};
+            },
+            [&](int c, int j, uint32_t p) { g[p] = m[4 * c + j] ^ flip; });
     }
 };
 

@@ -102,7 +102,8 @@ __device__ __forceinline__ void split_from_rows(const uint32_t* rows, const Tile
     e = 0;
     if ((uint32_t)lane < g.Kg) {
         const uint32_t k = (uint32_t)lane;
-        const uint32_t nk = (uint32_t)min(L, g.glen - (uint64_t)k * L);
+        // every run but the group's last holds L keys (wave-uniform values)
+        const uint32_t nk = k + 1u < g.Kg ? (uint32_t)L : (uint32_t)(g.glen - (uint64_t)(g.Kg - 1u) * L);
         const uint32_t sk = g.first ? 0u : min(rows[k], nk);
         s = sk;
         e = g.last ? nk : min(max(rows[K + k], sk), nk);
