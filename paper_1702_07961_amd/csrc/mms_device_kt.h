@@ -398,8 +398,8 @@ __device__ __forceinline__ void merge_pair_range_kt(const Src& X, uint32_t aA, u
         }
         block_sort_kt<EM>(m, scr, lane);
         out.template put_block<EM>(out_base + o, min(N, d1 - o), m, lane);
-        p = (uint32_t)__builtin_amdgcn_readfirstlane((int)(p + u));
-        q = (uint32_t)__builtin_amdgcn_readfirstlane((int)(q + N - u));
+        p += u;   // u is a sum of ballot counts: the cursors stay wave-uniform
+        q += N - u;
     }
 }
 
