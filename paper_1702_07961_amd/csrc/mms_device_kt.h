@@ -387,13 +387,18 @@ __device__ __forceinline__ void merge_pair_range_kt(const Src& X, uint32_t aA, u
             const uint32_t ra = la - pc, rb = lb - qc;
             T a[EM], b[EM];
             read_block<EM>(A, B, a, b);
+            if (ra < N) {   // one wave-uniform branch per run that ends inside the block
 #pragma unroll
-            for (int e = 0; e < EM; ++e) {
-                const uint32_t k = (uint32_t)e * kWave + (uint32_t)lane;
-                a[e] = k < ra ? a[e] : w_sentinel<T>();
-                b[e] = N - 1u - k < rb ? b[e] : w_sentinel<T>();
-                m[e] = w_min(a[e], b[e]);
+                for (int e = 0; e < EM; ++e)
+                    a[e] = (uint32_t)e * kWave + (uint32_t)lane < ra ? a[e] : w_sentinel<T>();
             }
+            if (rb < N) {
+#pragma unroll
+                for (int e = 0; e < EM; ++e)
+                    b[e] = N - 1u - ((uint32_t)e * kWave + (uint32_t)lane) < rb ? b[e] : w_sentinel<T>();
+            }
+#pragma unroll
+            for (int e = 0; e < EM; ++e) m[e] = w_min(a[e], b[e]);
             u = prefix_len_kt<EM, T>(a, b);
         }
         block_sort_kt<EM>(m, scr, lane);
