@@ -177,28 +177,32 @@ __device__ __forceinline__ void bitonic_merge_striped(El (&m)[EM], int lane) {
 // ---------------------------------------------------------------------------
 // Merge-path split inside LDS: the number p of elements of A = X[aA, aA+la)
 // among the first d elements of merge(A, B = X[aB, aB+lb)), A first on ties.
-// The wave probes 64 points per round with an odd stride, so the 64 reads of
-// one round fall in 64 distinct banks.
+// The wave probes 64 points per round, one per lane, with an odd stride, so
+// the 64 reads of one round fall in 64 distinct banks (for 64-bit keys, on
+// distinct bank pairs: 32 lanes are served per cycle and lane l covers words
+// 2(c + l*step) and 2(c + l*step) + 1).  A range of R > 1 candidates takes
+// ceil(log64 R) rounds: at most two for every merge tile here.  X is an LDS view
+// (key(i)); keys are compared alone, A first on ties, which is the stable
+// order of the two runs.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t lds_corank2(const uint32_t* Xk, uint32_t aA, uint32_t la, uint32_t aB,
-                                                uint32_t lb, uint32_t d, int lane) {
+template <class View>
+__device__ __forceinline__ uint32_t lds_corank2_view(const View& X, uint32_t aA, uint32_t la, uint32_t aB,
+                                                     uint32_t lb, uint32_t d, int lane) {
     // wave-uniform bounds, kept in scalar registers
     uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(d > lb ? d - lb : 0u));
     uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)min(d, la));
     while (lo < hi) {
-        // 128 probes per round: probe q = lane + 64*j sits at lo + q*step.
-        // A probe past hi reads the last valid position instead (every
-        // index stays inside both runs) and does not count.
+        // probe lane sits at lo + lane*step; a probe past hi reads the last
+        // valid position instead (every index stays inside both runs) and
+        // does not count
         const uint32_t R = hi - lo;
-        const uint32_t step = ((R + 127u) >> 7) | 1u;
+        const uint32_t step = ((R + 63u) >> 6) | 1u;
         const uint32_t m0 = lo + (uint32_t)lane * step;
-        const uint32_t m1 = m0 + 64u * step;
-        const bool v0 = m0 < hi, v1 = m1 < hi;
-        const uint32_t c0 = v0 ? m0 : hi - 1u, c1 = v1 ? m1 : hi - 1u;
-        const bool p0 = v0 && Xk[aA + c0] <= Xk[aB + d - 1u - c0];
-        const bool p1 = v1 && Xk[aA + c1] <= Xk[aB + d - 1u - c1];
-        const uint32_t t = (uint32_t)__popcll(__ballot(p0)) + (uint32_t)__popcll(__ballot(p1));
-        const uint32_t nvalid = (uint32_t)__popcll(__ballot(v0)) + (uint32_t)__popcll(__ballot(v1));
+        const bool v0 = m0 < hi;
+        const uint32_t c0 = v0 ? m0 : hi - 1u;
+        const bool p0 = v0 && X.key(aA + c0) <= X.key(aB + d - 1u - c0);
+        const uint32_t t = (uint32_t)__popcll(__ballot(p0));
+        const uint32_t nvalid = (uint32_t)__popcll(__ballot(v0));
         const uint32_t nlo = t > 0 ? lo + (t - 1u) * step + 1u : lo;
         const uint32_t nhi = t < nvalid ? lo + t * step : hi;
         lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)nlo);
@@ -207,33 +211,16 @@ __device__ __forceinline__ uint32_t lds_corank2(const uint32_t* Xk, uint32_t aA,
     return lo;
 }
 
-// lds_corank2 over any LDS view (keys compared alone, A first on ties, which
-// is the stable order of the two runs).  For 64-bit keys the probes at an odd
-// stride also fall on distinct bank pairs: 32 lanes are served per cycle and
-// lane l covers words 2(c + l*step) and 2(c + l*step) + 1.
-template <class View>
-__device__ __forceinline__ uint32_t lds_corank2_view(const View& X, uint32_t aA, uint32_t la, uint32_t aB,
-                                                     uint32_t lb, uint32_t d, int lane) {
-    uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(d > lb ? d - lb : 0u));
-    uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)min(d, la));
-    while (lo < hi) {
-        const uint32_t R = hi - lo;
-        const uint32_t step = ((R + 127u) >> 7) | 1u;
-        const uint32_t m0 = lo + (uint32_t)lane * step;
-        const uint32_t m1 = m0 + 64u * step;
-        const bool v0 = m0 < hi, v1 = m1 < hi;
-        const uint32_t c0 = v0 ? m0 : hi - 1u, c1 = v1 ? m1 : hi - 1u;
-        const bool p0 = v0 && X.key(aA + c0) <= X.key(aB + d - 1u - c0);
-        const bool p1 = v1 && X.key(aA + c1) <= X.key(aB + d - 1u - c1);
-        const uint32_t t = (uint32_t)__popcll(__ballot(p0)) + (uint32_t)__popcll(__ballot(p1));
-        const uint32_t nvalid = (uint32_t)__popcll(__ballot(v0)) + (uint32_t)__popcll(__ballot(v1));
-        const uint32_t nlo = t > 0 ? lo + (t - 1u) * step + 1u : lo;
-        const uint32_t nhi = t < nvalid ? lo + t * step : hi;
-        lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)nlo);
-        hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)nhi);
-    }
-    return lo;
+// lds_corank2_view over a plain array of 32-bit keys.
+struct KeysView {
+    const uint32_t* k;
+    __device__ __forceinline__ uint32_t key(uint32_t i) const { return k[i]; }
+};
+__device__ __forceinline__ uint32_t lds_corank2(const uint32_t* Xk, uint32_t aA, uint32_t la, uint32_t aB,
+                                                uint32_t lb, uint32_t d, int lane) {
+    return lds_corank2_view(KeysView{Xk}, aA, la, aB, lb, d, lane);
 }
+
 // ---------------------------------------------------------------------------
 // Merge outputs [d0, d1) of the pair (A, B) in blocks of N = 64*EM.  Each
 // block reads the next N candidates of A (ascending) and of B (descending),
