@@ -112,18 +112,36 @@ __device__ __forceinline__ void split_from_rows(const uint32_t* rows, const Tile
 
 // Rows t and t+1 of the split table (2K consecutive words; the table has a
 // row past the last tile) copied into LDS by the memory unit, one word per
-// lane, without passing through registers.  The copy is complete once the
-// wave's vector memory counter has drained past it.
+// lane, without passing through registers.  The copy is issued in inline
+// assembly (saving and restoring M0, which holds its LDS address) so that the
+// compiler does not track it: after a tracked copy into LDS the compiler
+// makes the next LDS read of every wave wait for all of the wave's
+// outstanding memory operations, since it cannot tell that the read does not
+// touch the copy's target, and here that read comes on every tile while the
+// previous tile's stores are still in flight.  The caller waits for the copy
+// itself: wave 0, the only wave that issues it, drains its memory counter on
+// every path between the copy and the next read of the rows.
 __device__ __forceinline__ void fetch_rows_async(const uint32_t* __restrict__ table, uint64_t t, uint32_t K,
                                                  uint32_t* rows, int lane) {
     // the rows' address as a wave-uniform base plus a per-lane offset
     const uint64_t base = (uint64_t)(uintptr_t)(table + t * K);
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(base >> 32));
-    const uint32_t* row = (const uint32_t*)(uintptr_t)(((uint64_t)hi << 32) | lo);
-    if ((uint32_t)lane < 2u * K)
-        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(row + (uint32_t)lane),
-                                         (__attribute__((address_space(3))) void*)rows, 4, 0, 0);
+    const uint64_t row = ((uint64_t)hi << 32) | lo;
+    const uint32_t lds = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uintptr_t)rows);
+    if ((uint32_t)lane < 2u * K) {
+        uint32_t saved;
+        asm volatile(
+            "s_mov_b32 %0, m0\n\t"
+            "s_mov_b32 m0, %2\n\t"
+            "s_nop 0\n\t"
+            "global_load_lds_dword %1, %3\n\t"
+            "s_nop 0\n\t"
+            "s_mov_b32 m0, %0"
+            : "=&s"(saved)
+            : "v"(4u * (uint32_t)lane), "s"(lds), "s"(row)
+            : "memory");
+    }
 }
 
 // words of one piece table (with its chunk table)
@@ -145,8 +163,9 @@ __device__ __forceinline__ void build_chunks(const Meta& m, uint32_t Kg, int lan
 
 // The whole piece table by one wave (the pipeline's prologue).
 template <int W>
-__device__ __forceinline__ void build_meta(const Meta& m, uint32_t s, uint32_t e, const TileGeo& g, int lane) {
-    build_pieces(m, s, e, g.Kg, g.cnt, lane);
+__device__ __forceinline__ void build_meta(const Meta& m, uint32_t s, uint32_t e, const TileGeo& g, uint64_t L,
+                                          int lane) {
+    build_pieces(m, s, e, g.Kg, g.cnt, L, lane);
     lds_wave_sync();
     build_chunks(m, g.Kg, lane);
     build_plan<W>(m, g.Kg, lane);
@@ -212,27 +231,57 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
         }
         const uint32_t slots = m.sbeg[g.Kg];
         const uint32_t glen = (uint32_t)g.glen;
+        const uint32_t Kg = g.Kg;
         cgu32* gsrc = gptr(g.src) + g.gb;
+        // Each chunk's piece in three rounds of LDS reads, the reads of all
+        // of a thread's chunks issued together in each round: the chunk
+        // table gives the piece holding slot 64*floor(P/64), the next two
+        // piece starts move it on by up to two pieces (further only past a
+        // piece shorter than 64 slots, in a loop that seldom runs), and the
+        // piece's source offset gives the chunk's position in the group.
+        // Every lane loads (a lane past the tile's last chunk reads chunk 0
+        // again and discards it), so no load sits under a branch.
+        uint32_t P[PC], k[PC];
+        bool used[PC], more[PC];
 #pragma unroll
         for (int r = 0; r < PC; ++r) {
-            // every lane loads (a lane past the tile's last chunk reads chunk
-            // 0 again and discards it), so no load sits under a branch
             const uint32_t P0 = 4u * ((uint32_t)r * NT + tid);
-            const bool used = P0 < slots;
-            const uint32_t P = used ? P0 : 0u;
-            uint32_t k = m.cseg[P >> 6];
-            while (k + 1u < g.Kg && m.sbeg[k + 1u] <= P) ++k;
-            const uint32_t q = k * (uint32_t)L + m.start[k] + (P - m.sbeg[k]);   // inside the group
-            const uint32_t d = q + 4u > glen ? q + 4u - glen : 0u;                 // 0..3
+            used[r] = P0 < slots;
+            P[r] = used[r] ? P0 : 0u;
+            k[r] = m.cseg[P[r] >> 6];
+        }
+#pragma unroll
+        for (int r = 0; r < PC; ++r) {
+            const uint32_t k0 = k[r];
+            const uint32_t s1 = m.sbeg[k0 + 1u], s2 = m.sbeg[min(k0 + 2u, kMaxFanout)];
+            const bool a1 = k0 + 1u < Kg && s1 <= P[r];
+            const bool a2 = k0 + 2u < Kg && s2 <= P[r];   // implies a1: piece starts ascend
+            k[r] = k0 + (uint32_t)a1 + (uint32_t)a2;
+            more[r] = a2;
+        }
+#pragma unroll
+        for (int r = 0; r < PC; ++r)
+            if (more[r])
+                while (k[r] + 1u < Kg && m.sbeg[k[r] + 1u] <= P[r]) ++k[r];
+#pragma unroll
+        for (int r = 0; r < PC; ++r) {
+            const uint32_t q = m.src0[k[r]] + P[r];                    // inside the group
+            const uint32_t d = q + 4u > glen ? q + 4u - glen : 0u;     // 0..3
             pf_val[r] = *reinterpret_cast<cgu32x4a4*>(gsrc + (q - d));
-            pf_dst[r] = used ? (P | (d << 30)) : 0xFFFFFFFFu;
+            pf_dst[r] = used[r] ? (P[r] | (d << 30)) : 0xFFFFFFFFu;
         }
     };
     auto store_loads = [&](uint32_t* X) {
 #pragma unroll
         for (int r = 0; r < PC; ++r) {
+            // every lane's load is waited for here, not only the stored
+            // ones: otherwise the compiler cannot tell, where the next
+            // tile's loads reuse these registers, that no load into them is
+            // outstanding, and waits there for all of the wave's memory
+            // operations (the previous tile's stores included)
+            u32x4a4 v = pf_val[r];
+            asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
             if (pf_dst[r] != 0xFFFFFFFFu) {
-                u32x4a4 v = pf_val[r];
                 const uint32_t d = pf_dst[r] >> 30;
                 if (d) {   // key j of the chunk is component j + d
                     v.x = d == 1u ? v.y : d == 2u ? v.z : v.w;
@@ -259,15 +308,15 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
         if (wave == 0) {
             uint32_t s, e;
             load_split(table, t, g, L, K, lane, s, e);
-            build_meta<W>(meta(0), s, e, g, lane);
+            build_meta<W>(meta(0), s, e, g, L, lane);
             if (t + G < tiles) {
                 const TileGeo g1 = tile_geo(ph, b, t + G, ra, lL);
                 load_split(table, t + G, g1, L, K, lane, s, e);
-                build_meta<W>(meta(1), s, e, g1, lane);
+                build_meta<W>(meta(1), s, e, g1, L, lane);
                 if (t + 2 * G < tiles) {
                     const TileGeo gp = tile_geo(ph, b, t + 2 * G, ra, lL);
                     load_split(table, t + 2 * G, gp, L, K, lane, s, e);
-                    build_pieces(meta(2), s, e, gp.Kg, gp.cnt, lane);
+                    build_pieces(meta(2), s, e, gp.Kg, gp.cnt, L, lane);
                     if (t + 3 * G < tiles) fetch_rows_async(table, t + 3 * G, K, rows, lane);
                 }
             }
@@ -303,7 +352,7 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
             const TileGeo g3 = tile_geo(ph, b, t3, ra, lL);
             uint32_t s3, e3;
             split_from_rows(rows, g3, L, K, lane, s3, e3);
-            build_pieces(meta(nxt(nxt(nxt(cur)))), s3, e3, g3.Kg, g3.cnt, lane);
+            build_pieces(meta(nxt(nxt(nxt(cur)))), s3, e3, g3.Kg, g3.cnt, L, lane);
             if (t3 + G < tiles) fetch_rows_async(table, t3 + G, K, rows, lane);
         }
         // waves 1 and 2: chunk table and wave plan of tile t+2G
@@ -314,10 +363,11 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
             else build_plan<W>(m2, kg2, lane);
         }
         // the next tile's keys go in flight now and land during the last level
-        bool issued = false, stored = false;
         if (has_next) {
             issue_loads(tile_geo(ph, b, tn, ra, lL), mn);
-            issued = true;
+        } else {
+#pragma unroll
+            for (int r = 0; r < PC; ++r) pf_dst[r] = 0xFFFFFFFFu;
         }
 
         uint32_t* X = in;
@@ -332,46 +382,37 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
         const int pe = W == 8 ? (wave < 4 ? 7 - wave : wave - 4) : wave;
         uint32_t nlev = 0;
         while ((1u << nlev) < g.Kg) ++nlev;
+        // Every tile stores the next tile's keys exactly once, on code every
+        // path back to the loop head passes through (no flag or branch decides
+        // it), into the buffer this tile's last step does not read: the
+        // compiler then knows that the prefetch registers are free at the
+        // loop head and issues the next tile's loads without waiting for this
+        // tile's stores.  Wave 0 first drains its memory counter: the split-
+        // table rows it copied into LDS at the top of this tile are read at
+        // the top of the next.
+        const bool vec = ((uintptr_t)(dst + obase) & 15u) == 0;
+        for (uint32_t lvl = 0; lvl + 1u < nlev; ++lvl) {
+            LdsSinkKeys out{Y};
+            merge_level_planned<EM>(X, mc.sbeg, mc.plen, mc.plan, g.Kg, lvl, out, wscr, pe, lane);
+            lds_barrier();
+            if (lvl == 0) __builtin_amdgcn_s_setprio(0);
+            uint32_t* tmp = X; X = Y; Y = tmp;
+        }
+        // the last step reads X (or nothing) and stores to memory; Y is free
+        if (wave == 0) vm_drain();
+        store_loads(Y);
         if (g.Kg == 1) {   // a lone run: its tile is already in order
             for (uint32_t j = tid; j < g.cnt; j += NT) gptr(dst)[obase + j] = gptr(g.src)[obase + j] ^ flip_out;
         } else {
-            const bool vec = ((uintptr_t)(dst + obase) & 15u) == 0;
-            for (uint32_t lvl = 0; lvl < nlev; ++lvl) {
-                const bool last = lvl + 1u == nlev;
-                // from the second level on, the last level reads the buffer the
-                // level before wrote, and the other one is free: the next
-                // tile's keys go there, and the barrier after the last level
-                // publishes them
-                if (last && lvl > 0 && issued) {
-                    if (wave == 0) vm_drain();
-                    store_loads(Y);
-                    stored = true;
-                }
-                if (last) {
-                    GlobalSinkKeys out{dst + obase, flip_out, g.cnt, vec};
-                    merge_level_planned<EM>(X, mc.sbeg, mc.plen, mc.plan, g.Kg, lvl, out, wscr, pe, lane);
-                } else {
-                    LdsSinkKeys out{Y};
-                    merge_level_planned<EM>(X, mc.sbeg, mc.plen, mc.plan, g.Kg, lvl, out, wscr, pe, lane);
-                }
-                lds_barrier();
-                if (lvl == 0) __builtin_amdgcn_s_setprio(0);
-                uint32_t* tmp = X; X = Y; Y = tmp;
-            }
+            GlobalSinkKeys out{dst + obase, flip_out, g.cnt, vec};
+            merge_level_planned<EM>(X, mc.sbeg, mc.plen, mc.plan, g.Kg, nlev - 1u, out, wscr, pe, lane);
         }
-        if (g.Kg == 1) __builtin_amdgcn_s_setprio(0);
+        lds_barrier();   // publishes the next tile's keys
+        __builtin_amdgcn_s_setprio(0);
         if (!has_next) break;
-        if (stored) {
-            // after the level loop (and its final swap) X holds the next
-            // tile's keys and Y is the buffer the last level read
-            in = X;
-            other = Y;
-        } else {
-            lds_barrier();        // every wave is done reading this tile's LDS
-            if (wave == 0) vm_drain();
-            store_loads(in);
-            lds_barrier();
-        }
+        // the next tile's keys are in Y; X is the buffer this tile read last
+        in = Y;
+        other = X;
         t = tn;
         cur = nxt(cur);
     }

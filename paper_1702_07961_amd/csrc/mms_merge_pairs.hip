@@ -103,7 +103,7 @@ __global__ __launch_bounds__(W * 64, 4) void k_merge_pairs(Phase ph, Bufs b, Rou
     }
     if (wave == 0) {   // the other waves wait for this plan: it issues first
         __builtin_amdgcn_s_setprio(2);
-        build_pieces(mt, s, e, Kg, cnt, lane);
+        build_pieces(mt, s, e, Kg, cnt, L, lane);
         lds_wave_sync();
         build_plan<W>(mt, Kg, lane);
         __builtin_amdgcn_s_setprio(0);

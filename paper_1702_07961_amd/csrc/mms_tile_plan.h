@@ -10,10 +10,11 @@
 
 namespace mms {
 
-// Piece table of a tile, written by wave 0: start[k] (inside run k),
+// Piece table of a tile, written by one wave: src0[k] (the key in LDS slot
+// P of piece k comes from position src0[k] + P of the group, modulo 2^32),
 // plen[k] (prefix of piece lengths), sbeg[k] (4-aligned LDS offsets).
 struct Meta {
-    uint32_t* start;
+    uint32_t* src0;
     uint32_t* plen;
     uint32_t* sbeg;
     uint32_t* plan;   // [4 levels][16 waves][2]: each wave's work per level
@@ -103,13 +104,13 @@ __device__ __forceinline__ PieceLayout piece_layout(uint32_t s, uint32_t e, uint
     return {len, pl, sb};
 }
 
-// The piece layout written to the tile's table: start, plen and sbeg of
-// every run and their totals.
+// The piece layout written to the tile's table: src0, plen and sbeg of
+// every run (run k starts at k*L in its group) and their totals.
 __device__ __forceinline__ void build_pieces(const Meta& m, uint32_t s, uint32_t e, uint32_t Kg, uint32_t cnt,
-                                             int lane) {
+                                             uint64_t L, int lane) {
     const PieceLayout pc = piece_layout(s, e, Kg, cnt, lane);
     if ((uint32_t)lane < Kg) {
-        m.start[lane] = s;
+        m.src0[lane] = (uint32_t)((uint64_t)lane * L) + s - pc.sb;
         m.plen[lane] = pc.pl;
         m.sbeg[lane] = pc.sb;
     }
