@@ -522,6 +522,35 @@ __device__ __forceinline__ void merge_pair_range_keys(const uint32_t* X, uint32_
         }
         return;
     }
+    if (d0 == 0 && d1 == la + lb && la <= N && lb <= N && la + lb > N) {
+        // The whole pair in one read: A ascending and B descending, each
+        // padded with sentinels to N, form a bitonic sequence of 2N whose
+        // element-wise minimum and maximum halves hold the N smallest keys
+        // and the other la + lb - N (then sentinels), each half bitonic:
+        // two block sorts finish the pair, with no second read.  The reads
+        // stay below the end of B plus N, as in the blocks below.
+        const uint32_t* Ap = X + aA + (uint32_t)lane;
+        const uint32_t* Bp = X + aB + (N - 1u) - (uint32_t)lane;
+        uint32_t a[EM], b[EM], lo[EM], hi[EM];
+#pragma unroll
+        for (int e = 0; e < EM; ++e) {
+            a[e] = Ap[e * kWave];
+            b[e] = Bp[-(e * kWave)];
+        }
+#pragma unroll
+        for (int e = 0; e < EM; ++e) {
+            const uint32_t k = (uint32_t)e * kWave + (uint32_t)lane;
+            const uint32_t ak = k < la ? a[e] : kSentKey;
+            const uint32_t bk = N - 1u - k < lb ? b[e] : kSentKey;
+            lo[e] = min(ak, bk);
+            hi[e] = max(ak, bk);
+        }
+        block_sort_keys<EM>(lo, scr, lane);
+        out.template put_block<EM>(out_base, N, lo, lane);
+        block_sort_keys<EM>(hi, scr, lane);
+        out.template put_block<EM>(out_base + N, la + lb - N, hi, lane);
+        return;
+    }
     uint32_t p = lds_corank2(X, aA, la, aB, lb, d0, lane);
     uint32_t q = d0 - p;
     for (uint32_t o = d0; o < d1; o += N) {

@@ -12,9 +12,10 @@
 // holds a few chunks with their LDS destinations) and land in the LDS buffer
 // that tile t's last level does not read.  The piece table of a tile is
 // built in two steps one tile apart, by three waves besides their share of
-// the merge: wave 0 lays out the pieces of tile t+3G from split indices it
-// fetched one tile earlier with scalar loads, then waves 1 and 2 derive the
-// chunk table and the per-level wave plan of tile t+2G from its layout.
+// the merge: wave 0 lays out the pieces of tile t+3G from split-table rows
+// the memory unit copied into LDS one tile earlier, then waves 1 and 2
+// derive the chunk table and the per-level wave plan of tile t+2G from its
+// layout.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
