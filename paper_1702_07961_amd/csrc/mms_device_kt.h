@@ -358,6 +358,29 @@ __device__ __forceinline__ void merge_pair_range_kt(const Src& X, uint32_t aA, u
         }
         return;
     }
+    if (d0 == 0 && d1 == la + lb && la <= N && lb <= N && la + lb > N) {
+        // the whole pair from one read, as in merge_pair_range_keys: the
+        // minimum and maximum halves of the bitonic sequence of A and
+        // reversed B (each padded with sentinels to N) are sorted apart; a
+        // sentinel orders after every element, so the second half's
+        // la + lb - N stored positions hold elements only
+        const auto A = X.from(aA + (uint32_t)lane);
+        const auto B = X.from(aB + (N - 1u) - (uint32_t)lane - (uint32_t)(EM - 1) * kWave);
+        T lo[EM], hi[EM];
+        read_block<EM>(A, B, lo, hi);
+#pragma unroll
+        for (int e = 0; e < EM; ++e) {
+            const uint32_t k = (uint32_t)e * kWave + (uint32_t)lane;
+            lo[e] = k < la ? lo[e] : w_sentinel<T>();
+            hi[e] = N - 1u - k < lb ? hi[e] : w_sentinel<T>();
+            w_cex(lo[e], hi[e]);
+        }
+        block_sort_kt<EM>(lo, scr, lane);
+        out.template put_block<EM>(out_base, N, lo, lane);
+        block_sort_kt<EM>(hi, scr, lane);
+        out.template put_block<EM>(out_base + N, la + lb - N, hi, lane);
+        return;
+    }
     uint32_t p = X.corank(aA, la, aB, lb, d0, lane);
     uint32_t q = d0 - p;
     for (uint32_t o = d0; o < d1; o += N) {
