@@ -33,6 +33,8 @@ buffer and written to another, workspace preallocated.  Prints one JSON line:
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                        [--no-configs] [--no-batched] [--no-serving]
+       one other workload instead of the headline: [--n N] [--family F]
+       [--swaps S] [--i32] [--pairs] [--u64] [--mergepath]
 """
 from __future__ import annotations
 
@@ -494,6 +496,8 @@ def main():
     ap.add_argument("--swaps", type=int, default=0, help="random pair swaps of the nearly-sorted family")
     ap.add_argument("--i32", action="store_true", help="int32 keys (signed order)")
     ap.add_argument("--pairs", action="store_true", help="stable (key, index) pairs")
+    ap.add_argument("--u64", action="store_true", help="64-bit keys (uniform family only; with --pairs, "
+                    "(uint64, uint64) pairs)")
     ap.add_argument("--mergepath", action="store_true",
                     help="time the merge-path baseline instead of the multiway sort (keys only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -516,15 +520,22 @@ def main():
     if args.mergepath and args.pairs:
         print("bench.py: the merge-path baseline sorts keys only", file=sys.stderr)
         sys.exit(2)
-    headline = (args.family == "uniform" and not args.i32 and not args.pairs and not args.mergepath and n == N_KEYS)
-    x_host = make_input(mmsgen, np, args.family, n, args.swaps)
+    if args.u64 and (args.family != "uniform" or args.i32 or args.mergepath):
+        print("bench.py: --u64 takes uniform unsigned keys and the multiway sort only", file=sys.stderr)
+        sys.exit(2)
+    headline = (args.family == "uniform" and not args.i32 and not args.pairs and not args.mergepath and
+                not args.u64 and n == N_KEYS)
+    if args.u64:
+        x_host = mmsgen.splitmix64(mmsgen.seed_for(15, 61 if args.pairs else 60), n)
+    else:
+        x_host = make_input(mmsgen, np, args.family, n, args.swaps)
     m = measure(mms, torch, np, x_host, pairs=args.pairs, i32=args.i32, steps=args.steps, warmup=args.warmup,
-                kind="mergepath" if args.mergepath else "mms")
+                kind="mergepath" if args.mergepath else ("mms64" if args.u64 else "mms"))
     copy_gbs = copy_probe(mms, torch, n)
 
     fam = args.family + (f" ({args.swaps} swaps)" if args.family == "nearly" else "")
     workload = (f"plain {'stable pair' if args.pairs else 'keys-only'} sort of {n} {fam} "
-                f"{'int32' if args.i32 else 'uint32'} keys, ascending"
+                f"{'uint64' if args.u64 else 'int32' if args.i32 else 'uint32'} keys, ascending"
                 + (", merge-path baseline" if args.mergepath else ""))
     if headline:
         workload = "plain sort of 1e8 uniform uint32 keys, keys only, ascending"
@@ -542,7 +553,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("i32" if args.i32 else "u32") + ("+u32 pairs" if args.pairs else ""),
+        "dtype": ("u64" + ("+u64 pairs" if args.pairs else "")) if args.u64 else
+                 (("i32" if args.i32 else "u32") + ("+u32 pairs" if args.pairs else "")),
         "data": "synthetic",
         "config": {"workload": workload,
                    "n": n, "input": f"{fam}, splitmix64 seed 0x4D4D5320",
@@ -557,7 +569,7 @@ def main():
                    "copy_probe_GBps": round(copy_gbs, 1)},
         "paper_context": PAPER_CONTEXT,
     }
-    if not args.no_cpu and not args.pairs:
+    if not args.no_cpu and not args.pairs and not args.u64:
         rec["cpu_baseline"] = cpu_baseline(x_host, args.i32)
     del x_host
     if headline and not args.no_configs:
