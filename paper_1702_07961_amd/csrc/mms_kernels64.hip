@@ -379,8 +379,8 @@ __global__ __launch_bounds__(W * 64, 4) void k_merge64_keys(Phase64 ph, Bufs64 b
     const U64SinkGlobal gout{dst + obase, flip_out, cnt, vec};
     for (uint32_t lvl = 0; lvl < nlev; ++lvl) {
         const U64Src in{X};
-        if (lvl + 1u == nlev) merge_level_kt<EM>(in, mt, Kg, lvl, gout, wscr, wave, lane);
-        else merge_level_kt<EM>(in, mt, Kg, lvl, U64SinkLds{Y}, wscr, wave, lane);
+        if (lvl + 1u == nlev) merge_level_kt<EM>(in, mt, Kg, lvl, gout, wscr, plan_entry<W>(wave), lane);
+        else merge_level_kt<EM>(in, mt, Kg, lvl, U64SinkLds{Y}, wscr, plan_entry<W>(wave), lane);
         lds_barrier();
         uint64_t* tmp = X; X = Y; Y = tmp;
     }

@@ -374,13 +374,7 @@ __global__ __launch_bounds__(W * 64, MINW) void k_merge_keys(Phase ph, Bufs b, R
         uint32_t* X = in;
         uint32_t* Y = other;
         const uint64_t obase = g.gb + g.obeg;
-        // Plan entry of this wave.  Waves w and w+4 share a SIMD, and an
-        // entry costs more the later its outputs lie in its pair (those
-        // blocks reach the runs' ends and mask the positions past them), at
-        // every level from the second on.  With eight waves, SIMD s runs
-        // entries 7-s (on the older wave, which the SIMD serves first) and s,
-        // so each SIMD gets one later and one earlier entry.
-        const int pe = W == 8 ? (wave < 4 ? 7 - wave : wave - 4) : wave;
+        const int pe = plan_entry<W>(wave);   // balanced over the SIMDs
         uint32_t nlev = 0;
         while ((1u << nlev) < g.Kg) ++nlev;
         // Every tile stores the next tile's keys exactly once, on code every

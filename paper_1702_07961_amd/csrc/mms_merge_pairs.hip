@@ -113,6 +113,7 @@ __global__ __launch_bounds__(W * 64, 4) void k_merge_pairs(Phase ph, Bufs b, Rou
 
     uint32_t nlev = 0;
     while ((1u << nlev) < Kg) ++nlev;
+    const int pe = plan_entry<W>(wave);   // balanced over the SIMDs
     uint32_t* Xk = K0;
     uint16_t* Xt = T0;
     uint32_t* Yk = K1;
@@ -123,12 +124,12 @@ __global__ __launch_bounds__(W * 64, 4) void k_merge_pairs(Phase ph, Bufs b, Rou
         const bool last = lvl + 1u == nlev;
         if (lvl == 0) {
             const KtSrcLoaded X{Xk};
-            if (last) merge_level_kt<kEMP>(X, mt, Kg, lvl, gout, wscr, wave, lane);
-            else merge_level_kt<kEMP>(X, mt, Kg, lvl, KtSinkLds{Yk, Yt}, wscr, wave, lane);
+            if (last) merge_level_kt<kEMP>(X, mt, Kg, lvl, gout, wscr, pe, lane);
+            else merge_level_kt<kEMP>(X, mt, Kg, lvl, KtSinkLds{Yk, Yt}, wscr, pe, lane);
         } else {
             const KtSrcTagged X{Xk, Xt};
-            if (last) merge_level_kt<kEMP>(X, mt, Kg, lvl, gout, wscr, wave, lane);
-            else merge_level_kt<kEMP>(X, mt, Kg, lvl, KtSinkLds{Yk, Yt}, wscr, wave, lane);
+            if (last) merge_level_kt<kEMP>(X, mt, Kg, lvl, gout, wscr, pe, lane);
+            else merge_level_kt<kEMP>(X, mt, Kg, lvl, KtSinkLds{Yk, Yt}, wscr, pe, lane);
         }
         lds_barrier();
         uint32_t* tk = Xk; Xk = Yk; Yk = tk;

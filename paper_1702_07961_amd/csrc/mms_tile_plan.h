@@ -87,6 +87,17 @@ __device__ __forceinline__ void build_plan(const Meta& m, uint32_t Kg, int lane)
     }
 }
 
+// The plan entry a wave merges.  Waves w and w+4 share a SIMD, which serves
+// the older one first, and an entry costs more the later its outputs lie in
+// its pair (those blocks reach the runs' ends and mask the positions past
+// them), at every level from the second on.  With eight waves, SIMD s runs
+// entries 7-s (on its older wave) and s, so each SIMD gets one later and one
+// earlier entry.
+template <int W>
+__device__ __forceinline__ int plan_entry(int wave) {
+    return W == 8 ? (wave < 4 ? 7 - wave : wave - 4) : wave;
+}
+
 // Piece layout of a tile of cnt outputs from Kg runs, in registers: lane
 // k < Kg, holding run k's split indices s <= e, gets its piece's length, its
 // first output (plen) and its 4-aligned first LDS slot (sbeg).
