@@ -136,3 +136,68 @@ def test_pairs_shape_sweep(mms, pairs_input, base):
         assert np.array_equal(host(gk), wku) and np.array_equal(host(gv), wvu), (K, base, "u32")
         gk, gv = mms.sort_pairs(xd, vd, i32=True)
         assert np.array_equal(host(gk), wks) and np.array_equal(host(gv), wvs), (K, base, "i32")
+
+
+# One-read merges of short pairs: a wave that owns a whole pair of runs of at
+# most one block each (N = 512 keys for the 64x8 shapes) merges it from a
+# single read.  At the first level of a 16-way tile each of the 8 pairs goes
+# to one wave, and the inputs fix how a tile's keys divide among the group's
+# 16 runs: evenly (every piece exactly N at 8192-key tiles, both runs of a
+# pair a full block), 2:1 and 1:2 within each pair (one piece a full block at
+# 6144-key tiles), a random division, the same keys in every run (ties
+# across the runs), and disjoint ranges (tiles drawing on one or two runs).
+def _group_pattern_input(base_tile, n_groups, seed):
+    """Groups of 16 base tiles (the runs of the first merge round), each
+    group over its own range of 16 * base_tile consecutive keys divided
+    among the runs by a pattern, every run holding base_tile keys in
+    shuffled order."""
+    K, bt = 16, base_tile
+    m = K * bt
+    perm_src = mmsgen.uniform_u32(mmsgen.seed_for(seed, 1), n_groups * m)
+    rnd = mmsgen.uniform_u32(mmsgen.seed_for(seed, 2), n_groups * m)
+    out = []
+    for j in range(n_groups):
+        kind = j % 6
+        base_val = np.uint64(j) * np.uint64(2 * m)
+        i = np.arange(m)
+        vals = i.astype(np.uint64) + base_val
+        if kind == 0:      # round robin: every run gets every 16th key
+            run = i % K
+        elif kind in (1, 2):
+            # per 24 keys: 2 to each heavier run of a pair, 1 to the other,
+            # until the heavier runs are full; the rest to the lighter ones
+            heavy = 0 if kind == 1 else 1
+            cyc, r = i // 24, i % 24
+            pair, slot = r // 3, r % 3
+            first = np.where(slot < 2, 2 * pair + heavy, 2 * pair + 1 - heavy)
+            cut = 12 * bt
+            rest = (i - cut) % (K // 2)
+            run = np.where(i < cut, first, 2 * rest + 1 - heavy)
+        elif kind == 3:    # a random division, bt keys per run
+            run = np.empty(m, dtype=np.int64)
+            run[np.argsort(rnd[j * m:(j + 1) * m], kind="stable")] = np.repeat(np.arange(K), bt)
+        elif kind == 4:    # the same keys in every run
+            vals = (i // K).astype(np.uint64) + base_val
+            run = i % K
+        else:              # disjoint ranges
+            run = i // bt
+        for k in range(K):
+            t = vals[run == k]
+            assert t.size == bt, (kind, k, t.size)
+            order = np.argsort(perm_src[j * m + k * bt:j * m + (k + 1) * bt], kind="stable")
+            out.append(t[order].astype(np.uint32))
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("variant,base,touts", [(2, 3, [8192, 6144]), (3, 6, [6144, 7424]), (1, 4, [8192])])
+def test_one_read_short_pairs(mms, variant, base, touts):
+    for tout in touts:
+        mms.set_tuning([(64, 16, tout, variant, base)])
+        bt = mms.plan(1 << 20).tile
+        x = _group_pattern_input(bt, 6, 40 + tout % 97)
+        x = np.concatenate([x, mmsgen.uniform_u32(mmsgen.seed_for(41, tout), 5001)])   # a ragged group
+        p = mms.plan(x.size)
+        assert p.fanout == 16 and p.merge_tile == tout and p.tile == bt
+        want = oracle.sort(x)
+        got = host(mms.sort(dev(x), i32=False))
+        assert np.array_equal(got, want), (variant, base, tout)
