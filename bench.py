@@ -54,7 +54,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "Gkeys/s sorting 1e8 uint32, % HBM roofline; p99 latency served vs per-call"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "merge_u32_1e8_traffic.json")
 KERNEL_SOURCES = ["paper_1702_07961_amd/csrc/mms_merge_keys.hip", "paper_1702_07961_amd/csrc/mms_device.h",
-                  "paper_1702_07961_amd/csrc/mms_internal.h"]
+                  "paper_1702_07961_amd/csrc/mms_internal.h", "paper_1702_07961_amd/csrc/mms_tile_plan.h"]
 
 
 def kernel_source_hash() -> str:

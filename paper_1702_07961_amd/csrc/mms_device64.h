@@ -80,15 +80,9 @@ __device__ __forceinline__ E64T shfl_xor(const E64T& e, int m) {
     return {shfl_xor_u64(e.k, m), shfl_xor_u32(e.t, m)};
 }
 
-// LDS views of a 64-bit merge buffer: key(i) and get(i) read slot i, put(i, e)
-// writes it (the interface merge_level reads and writes through).
-struct LdsK64 {
-    using El = E64;
-    uint64_t* k;
-    __device__ __forceinline__ uint64_t key(uint32_t i) const { return k[i]; }
-    __device__ __forceinline__ El get(uint32_t i) const { return {k[i]}; }
-    __device__ __forceinline__ void put(uint32_t i, const El& e) const { k[i] = e.k; }
-};
+// LDS views of a 64-bit key-value merge buffer: key(i) and get(i) read
+// slot i, put(i, e) writes it (the interface merge_level reads and writes
+// through).
 // Key-value merge levels: level 0 reads the keys as loaded, each element's
 // tag being its own slot; later levels read keys and 16-bit tags written by
 // the level before (tile slots stay below 2^16).
@@ -110,16 +104,9 @@ struct LdsKT64 {
     }
 };
 
-// Memory sinks of a tile's last merge level: position i < lim is stored
-// (with the signed-key mapping undone), positions past it are sentinels.
-struct GlobalSinkK64 {
-    uint64_t* k;
-    uint64_t flip;
-    uint32_t lim;
-    __device__ __forceinline__ void put(uint32_t i, const E64& e) const {
-        if (i < lim) gptr64(k)[i] = e.k ^ flip;
-    }
-};
+// Memory sink of a tile's last key-value merge level: position i < lim is
+// stored (with the signed-key mapping undone, the value gathered by tag),
+// positions past it are sentinels.
 struct GlobalSinkKT64 {
     uint64_t* k;
     uint64_t* v;

@@ -166,29 +166,28 @@ __global__ __launch_bounds__(256) void k_corank_tiles64(Phase64 ph, Bufs64 b, Ro
 }
 
 // ===========================================================================
-// K-way merge of one output tile (§4.2, §7): the tile's pieces of its
-// group's runs, bounded by the split indices of its first and last output,
-// are loaded into LDS back to back, merged pairwise level by level (log2 K
-// levels, 64x8-key or 64x4-pair blocks, every wave an equal share of each level's
-// outputs), and the last level is written to memory.
+// Key-value K-way merge of one output tile (§4.2, §7): the tile's pieces of
+// its group's runs, bounded by the split indices of its first and last
+// output, are loaded into LDS back to back, merged pairwise level by level
+// (log2 K levels, 64x4-pair blocks, every wave an equal share of each
+// level's outputs), and the last level is written to memory.
 // ===========================================================================
-template <int W, bool PAIRS>
-__global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundArgs ra,
-                                                    const uint32_t* __restrict__ table, uint64_t flip) {
-    constexpr int EM = PAIRS ? 4 : 8;   // a wave's share of a level: 256 pairs or 512 keys
+template <int W>
+__global__ __launch_bounds__(W * 64) void k_merge64_pairs(Phase64 ph, Bufs64 b, RoundArgs ra,
+                                                          const uint32_t* __restrict__ table, uint64_t flip) {
+    constexpr int EM = 4;   // a wave's share of a level: 256 pairs
     constexpr uint32_t NT = W * 64u;
     const uint32_t Tout = ra.Tout, K = ra.K;
     const uint64_t L = ra.L;
     extern __shared__ __align__(16) uint64_t smem64[];
-    // keys of the level buffers; pairs: their 16-bit tags and the values by
-    // slot as loaded
+    // keys of the level buffers, the values by slot as loaded and the keys'
+    // 16-bit tags
     uint64_t* Xk = smem64;
     uint64_t* Yk = smem64 + Tout;
-    uint64_t* V = PAIRS ? smem64 + 2 * Tout : nullptr;
-    uint16_t* Xt = PAIRS ? reinterpret_cast<uint16_t*>(smem64 + 3 * Tout) : nullptr;
-    uint16_t* Yt = PAIRS ? Xt + Tout : nullptr;
-    uint32_t* seg0 = PAIRS ? reinterpret_cast<uint32_t*>(Yt + Tout)
-                           : reinterpret_cast<uint32_t*>(smem64 + 2u * Tout);   // [kMaxFanout + 1]
+    uint64_t* V = smem64 + 2 * Tout;
+    uint16_t* Xt = reinterpret_cast<uint16_t*>(smem64 + 3 * Tout);
+    uint16_t* Yt = Xt + Tout;
+    uint32_t* seg0 = reinterpret_cast<uint32_t*>(Yt + Tout);                             // [kMaxFanout + 1]
     uint32_t* start = seg0 + kMaxFanout + 1;                                            // [kMaxFanout]
 
     const int lane = threadIdx.x & 63;
@@ -212,7 +211,7 @@ __global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundA
     if (Kg == 1) {   // a lone run: its tile is already in order
         for (uint32_t j = threadIdx.x; j < cnt; j += NT) {
             gptr64(dst_k)[obase + j] = gptr64(src_k)[obase + j] ^ flip_out;
-            if constexpr (PAIRS) gptr64(dst_v)[obase + j] = gptr64(src_v)[obase + j];
+            gptr64(dst_v)[obase + j] = gptr64(src_v)[obase + j];
         }
         return;
     }
@@ -231,7 +230,7 @@ __global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundA
     const uint32_t incl = min(row16_incl_sum(len), cnt);   // piece k ends at seg0[k + 1]
     {
         // the pieces, concatenated, go into LDS by the memory unit: 64 words
-        // (32 elements) of keys (and of values) per instruction, no register
+        // (32 elements) of keys and of values per instruction, no register
         // holding them, every chunk in flight at once; chunks are dealt to
         // the waves round-robin in piece order
         uint32_t cbase = 0;
@@ -247,9 +246,8 @@ __global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundA
                 if (j0 + (uint32_t)lane < w1) {
                     dma_dword(reinterpret_cast<const uint32_t*>(src_k) + run0 + 64u * c, (uint32_t)lane,
                               reinterpret_cast<uint32_t*>(Xk) + j0);
-                    if constexpr (PAIRS)
-                        dma_dword(reinterpret_cast<const uint32_t*>(src_v) + run0 + 64u * c, (uint32_t)lane,
-                                  reinterpret_cast<uint32_t*>(V) + j0);
+                    dma_dword(reinterpret_cast<const uint32_t*>(src_v) + run0 + 64u * c, (uint32_t)lane,
+                              reinterpret_cast<uint32_t*>(V) + j0);
                 }
             }
             cbase += nch;
@@ -267,21 +265,15 @@ __global__ __launch_bounds__(W * 64) void k_merge64(Phase64 ph, Bufs64 b, RoundA
 
     for (uint32_t lvl = 0; (1u << lvl) < Kg; ++lvl) {
         const bool last = (2u << lvl) >= Kg;
-        if constexpr (PAIRS) {
-            const GlobalSinkKT64 gout{dst_k + obase, dst_v + obase, V, flip_out, cnt};
-            if (lvl == 0) {
-                const LdsKT64Loaded X{Xk};
-                if (last) merge_level<EM>(X, seg0, Kg, lvl, cnt, gout, wave, W, lane);
-                else merge_level<EM>(X, seg0, Kg, lvl, cnt, LdsKT64{Yk, Yt}, wave, W, lane);
-            } else {
-                const LdsKT64 X{Xk, Xt};
-                if (last) merge_level<EM>(X, seg0, Kg, lvl, cnt, gout, wave, W, lane);
-                else merge_level<EM>(X, seg0, Kg, lvl, cnt, LdsKT64{Yk, Yt}, wave, W, lane);
-            }
+        const GlobalSinkKT64 gout{dst_k + obase, dst_v + obase, V, flip_out, cnt};
+        if (lvl == 0) {
+            const LdsKT64Loaded X{Xk};
+            if (last) merge_level<EM>(X, seg0, Kg, lvl, cnt, gout, wave, W, lane);
+            else merge_level<EM>(X, seg0, Kg, lvl, cnt, LdsKT64{Yk, Yt}, wave, W, lane);
         } else {
-            const LdsK64 X{Xk};
-            if (last) merge_level<EM>(X, seg0, Kg, lvl, cnt, GlobalSinkK64{dst_k + obase, flip_out, cnt}, wave, W, lane);
-            else merge_level<EM>(X, seg0, Kg, lvl, cnt, LdsK64{Yk}, wave, W, lane);
+            const LdsKT64 X{Xk, Xt};
+            if (last) merge_level<EM>(X, seg0, Kg, lvl, cnt, gout, wave, W, lane);
+            else merge_level<EM>(X, seg0, Kg, lvl, cnt, LdsKT64{Yk, Yt}, wave, W, lane);
         }
         lds_barrier();
         uint64_t* tmp = Xk; Xk = Yk; Yk = tmp;
@@ -434,11 +426,11 @@ hipError_t launch_merge64(bool pairs, const Phase64& ph, const Bufs64& b, const 
         hipLaunchKernelGGL((k_merge64_keys<W>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, ra, table, flip);
         return hipGetLastError();
     }
-    // keys 2 x Tout; pairs: values Tout and 16-bit tags 2 x Tout more
+    // keys 2 x Tout, values Tout and 16-bit tags 2 x Tout
     const size_t lds = 28u * ra.Tout + (2u * kMaxFanout + 4u) * sizeof(uint32_t);
-    hipError_t e = allow_lds64((const void*)k_merge64<W, true>, lds);
+    hipError_t e = allow_lds64((const void*)k_merge64_pairs<W>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_merge64<W, true>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, ra, table, flip);
+    hipLaunchKernelGGL((k_merge64_pairs<W>), dim3((unsigned)ph.tiles), dim3(W * 64), lds, s, ph, b, ra, table, flip);
     return hipGetLastError();
 }
 
