@@ -76,7 +76,10 @@ using CorankLds = CorankLdsT<uint32_t>;
 // sum(hi - lo) < K, the sub-blocks of h' = h/2^s that can still be inside
 // are [2^s lo, 2^s hi + 2^s - 2] (sub-block 2^s(hi+1) - 1 being inside would
 // put c_k past block hi), at most (2^(s+1) - 1)K - 2^s in all: 3K - 2 <= 46
-// for K <= 16, 7K - 4 <= 59 for K <= 9, one per lane either way.
+// for K <= 16, 7K - 4 <= 59 for K <= 9, one per lane either way.  The first
+// round starts from lo = hi = 0, so only (2^s - 1)K candidates exist and it
+// takes the largest s with (2^s - 1)K <= 64 (2 for K <= 16, 3 for K <= 9,
+// 4 for K <= 4, 5 for K = 2): one dependent round fewer, or more.
 //
 // The candidates of a round sit in lanes run by run (run k's in lanes off_k ..
 // off_k + cnt_k - 1, in block order), so lane order is (run, block) order and
@@ -98,8 +101,8 @@ __device__ uint32_t corank_rounds(const KeyT* __restrict__ keys, uint64_t gb, ui
     uint32_t lo = 0, hi = 0;   // lane k
     uint32_t slo = 0;          // sum of lo over the runs
     uint32_t tag = 0;
+    int s = min(l, Kg <= 2u ? 5 : Kg <= 4u ? 4 : Kg <= 9u ? 3 : 2);   // the first round's step
     while (l > 0) {
-        const int s = STEP == 1 ? 1 : min(STEP, l);
         l -= s;
         tag += 256u;
         const uint32_t nb = nk >> l;   // full blocks of run k at resolution 2^l
@@ -160,6 +163,7 @@ __device__ uint32_t corank_rounds(const KeyT* __restrict__ keys, uint64_t gb, ui
         lo = jlo + bits_in(blo, off, cnt);
         hi = jlo + bits_in(bhi, off, cnt);
         slo = sj + (uint32_t)__popcll(blo);
+        s = STEP == 1 ? 1 : min(STEP, l);
     }
     return lo;
 }

@@ -176,7 +176,8 @@ def test_pairs_signed(mms):
                                         (16, 37, 16 * 37 * 3 - 5, True), (2, 5000, 12_000, False),
                                         (1, 64, 200, False), (7, 333, 7 * 333 + 5, True),
                                         (9, 4096, 9 * 4096 * 2 - 17, False), (8, 777, 8 * 777 * 2 + 3, True),
-                                        (10, 1000, 10 * 1000 + 1, True)])
+                                        (10, 1000, 10 * 1000 + 1, True), (3, 8192, 3 * 8192 * 2 + 1234, False),
+                                        (5, 500, 5 * 500 * 3 - 1, True)])
 def test_partition_against_oracle(mms, Kq, L, n, tie):
     x = (mmsgen.uniform_u32(21, n) % np.uint32(3)) if tie else mmsgen.uniform_u32(22, n)
     for s in range(0, n, L):
