@@ -89,6 +89,28 @@ def test_keys_base_shapes(mms, base, n):
         mms._lib.load_tuning(mms._lib.lib())
 
 
+@pytest.mark.parametrize("K,n,family", [(16, 2048 * 16 * 3 + 4321, "sixteen"), (16, 2048 * 16 * 16 * 2 - 7, "uniform"),
+                                         (4, 2048 * 4 ** 4 * 2 + 999, "sixteen"), (2, 2048 * 2 ** 6 * 3 + 5, "uniform"),
+                                         (2, 2048 * 2 ** 5 + 1, "sixteen")])
+def test_fanouts_ragged_groups(mms, K, n, family):
+    """Fan-outs 16, 4 and 2 on 2048-key base tiles and 4096-key merge tiles:
+    groups of 8 to 64 merge tiles, partitions refining one bit per round (16
+    runs) and several (at most 9 runs, also 3-run last rounds), ragged last
+    groups, runs of 2^11 to 2^17 keys, many equal keys; keys and stable pairs
+    against the oracle."""
+    x = mmsgen.family(family, mmsgen.seed_for(31, K * 1000 + n % 1000), n)
+    v = np.arange(n, dtype=np.uint32)
+    try:
+        mms.set_tuning([(64, K, 4096, 2, 0), (64, K, 4096, 0, 0, mms.MMS_PAIRS)])
+        assert np.array_equal(host(mms.sort(dev(x), i32=False)), oracle.sort(x))
+        gk, gv = mms.sort_pairs(dev(x), dev(v), i32=True)
+        ok, ov = oracle.sort(x, v, i32=True)
+        assert np.array_equal(host(gk), ok) and np.array_equal(host(gv), ov)
+    finally:
+        mms.set_tuning([])
+        mms._lib.load_tuning(mms._lib.lib())
+
+
 @pytest.mark.parametrize("pk,pbase", [(4, 0), (8, 3), (2, 3)])
 def test_pairs_own_tuning_entries(mms, pk, pbase):
     """Key-value sorts follow their own tuning entries while keys-only sorts
