@@ -2,9 +2,10 @@
 //
 //   tile_sort   base case (§4.3): sort tiles of T1 elements on chip
 //   corank      partition (§4.1): split indices of K sorted runs at a rank
-//   merge       K-way merge of one output tile through LDS (§4.2, §7),
-//               key-value path (the keys-only path is mms_merge_keys.hip)
 //   copy        streaming copy, the bandwidth probe
+//
+// The K-way merges of a round (§4.2, §7) are in mms_merge_keys.hip (keys
+// only) and mms_merge_pairs.hip (key-value).
 //
 // Every sorting kernel works on a Phase: a list of tiles, each inside one
 // segment (the plain sort is one segment).  Positions are segment-relative;
