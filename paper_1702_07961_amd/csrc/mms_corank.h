@@ -79,7 +79,7 @@ using CorankLds = CorankLdsT<uint32_t>;
 // for K <= 16, 7K - 4 <= 59 for K <= 9, one per lane either way.  The first
 // round starts from lo = hi = 0, so only (2^s - 1)K candidates exist and it
 // takes the largest s with (2^s - 1)K <= 64 (2 for K <= 16, 3 for K <= 9,
-// 4 for K <= 4, 5 for K = 2): one dependent round fewer, or more.
+// 4 for K <= 4, 5 for K <= 2): one dependent round fewer, or more.
 //
 // The candidates of a round sit in lanes run by run (run k's in lanes off_k ..
 // off_k + cnt_k - 1, in block order), so lane order is (run, block) order and
