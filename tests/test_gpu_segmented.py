@@ -50,6 +50,27 @@ def test_segmented_keys_ragged(mms, family):
     assert np.array_equal(got, oracle.sort_segments(x, off))
 
 
+@pytest.mark.parametrize("sizes", [[T * K * 3 + 11], [0, 0, 0], [1] * 300, [T] * 40, [T * K] * 5,
+                                   [0, T * K * K, 0]])
+def test_segmented_degenerate_batches(mms, sizes):
+    """One segment (the plain sort's plan), only empty segments, 300 one-key
+    segments, and segments that end exactly on base-tile and group
+    boundaries: keys and stable pairs equal their oracle segment by segment;
+    the keys past the last offset are not touched."""
+    off = offsets_of(sizes)
+    n = int(off[-1])
+    x = mmsgen.family("sixteen", mmsgen.seed_for(4, 20 + len(sizes)), n + 8)
+    guard = np.full(x.size, 0xA5A5A5A5, dtype=np.uint32)
+    out = dev(guard)
+    got = host(mms.segmented_sort(dev(x), off, out_keys=out, i32=False))
+    assert np.array_equal(got[:n], oracle.sort_segments(x[:n], off))
+    assert np.array_equal(got[n:], guard[n:])
+    v = np.arange(x.size, dtype=np.uint32)
+    gk, gv = mms.segmented_sort(dev(x), off, values=dev(v), i32=True)
+    ok, ov = oracle.sort_segments(x[:n], off, vals=v[:n], i32=True)
+    assert np.array_equal(host(gk)[:n], ok) and np.array_equal(host(gv)[:n], ov)
+
+
 def test_segmented_pairs_stable(mms):
     sizes = ragged_sizes()
     off = offsets_of(sizes)
