@@ -68,11 +68,25 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort_keys(Phase ph, Bufs b, uin
     uint32_t* out_k = tr.dst_k + base;
     const uint32_t flip_out = tr.final_pass ? flip : 0u;
 
+    // The wave sorts whatever it holds, so each lane loads four consecutive
+    // keys per 16-byte load (chunk c: positions c*256 + 4*lane ..), which
+    // covers the wave's CH keys in E/4 loads.
     Elem<false> r[E];
+    const bool vec_in = ((uintptr_t)in_k & 15u) == 0;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t j = (uint32_t)wave * CH + (uint32_t)e * 64u + ul;
-        r[e] = j < cnt ? Elem<false>{gptr(in_k)[j] ^ flip} : Elem<false>::sentinel();
+    for (uint32_t c = 0; c < Q; ++c) {
+        const uint32_t j = (uint32_t)wave * CH + c * 256u + 4u * ul;
+        if (vec_in && j + 4u <= cnt) {
+            const u32x4 v = *reinterpret_cast<const gu32x4*>(gptr(in_k) + j);
+            r[4 * c] = {v[0] ^ flip};
+            r[4 * c + 1] = {v[1] ^ flip};
+            r[4 * c + 2] = {v[2] ^ flip};
+            r[4 * c + 3] = {v[3] ^ flip};
+        } else {
+#pragma unroll
+            for (uint32_t q = 0; q < 4u; ++q)
+                r[4 * c + q] = j + q < cnt ? Elem<false>{gptr(in_k)[j + q] ^ flip} : Elem<false>::sentinel();
+        }
     }
     wave_sort_blocked<E>(r, lane);
 
