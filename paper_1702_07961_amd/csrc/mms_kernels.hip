@@ -172,15 +172,29 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort_pairs(Phase ph, Bufs b, ui
     uint32_t* out_v = tr.dst_v + base;
     const uint32_t flip_out = tr.final_pass ? flip : 0u;
 
+    // as in the keys-only base case, four consecutive pairs per 16-byte load
+    // (each tagged with its own tile position); values staged in LDS alike
     ElemKT r[E];
+    const bool vec_in = ((((uintptr_t)in_k) | (uintptr_t)in_v) & 15u) == 0;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t j = (uint32_t)wave * CH + (uint32_t)e * 64u + ul;
-        if (j < cnt) {
-            r[e] = ElemKT{kt_pack(gptr(in_k)[j] ^ flip, j)};
-            V[j] = gptr(in_v)[j];
+    for (uint32_t c = 0; c < Q; ++c) {
+        const uint32_t j = (uint32_t)wave * CH + c * 256u + 4u * ul;
+        if (vec_in && j + 4u <= cnt) {
+            const u32x4 k = *reinterpret_cast<const gu32x4*>(gptr(in_k) + j);
+            const u32x4 v = *reinterpret_cast<const gu32x4*>(gptr(in_v) + j);
+#pragma unroll
+            for (uint32_t q = 0; q < 4u; ++q) r[4 * c + q] = ElemKT{kt_pack(k[q] ^ flip, j + q)};
+            *reinterpret_cast<uint4*>(V + j) = make_uint4(v[0], v[1], v[2], v[3]);
         } else {
-            r[e] = ElemKT::sentinel();
+#pragma unroll
+            for (uint32_t q = 0; q < 4u; ++q) {
+                if (j + q < cnt) {
+                    r[4 * c + q] = ElemKT{kt_pack(gptr(in_k)[j + q] ^ flip, j + q)};
+                    V[j + q] = gptr(in_v)[j + q];
+                } else {
+                    r[4 * c + q] = ElemKT::sentinel();
+                }
+            }
         }
     }
     wave_sort_blocked<E>(r, lane);

@@ -69,19 +69,45 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort64(Phase64 ph, Bufs64 b, ui
     uint64_t* out_v = PAIRS ? (ph.dst_out ? b.out_v : b.ws_v) + base : nullptr;
     const uint64_t flip_out = ph.final_pass ? flip : 0ull;
 
+    // the wave sorts any arrangement of its keys, so each lane loads two
+    // consecutive elements per 16-byte load (chunk c: positions c*128 +
+    // 2*lane, +1); a pair's tag is its own tile position
+    typedef uint64_t v2u64 __attribute__((ext_vector_type(2)));
+    typedef const __attribute__((address_space(1))) v2u64 cgv2u64;
     El r[E];
+    const uint64_t* in_k = b.in_k + base;
+    const uint64_t* in_v = PAIRS ? b.in_v + base : b.in_k + base;
+    const bool vec_in = ((((uintptr_t)in_k) | (uintptr_t)in_v) & 15u) == 0;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t j = (uint32_t)wave * CH + (uint32_t)e * 64u + ul;
-        if (j < cnt) {
+    for (uint32_t c = 0; c < (uint32_t)E / 2u; ++c) {
+        const uint32_t j = (uint32_t)wave * CH + c * 128u + 2u * ul;
+        if (vec_in && j + 2u <= cnt) {
+            const v2u64 k = *reinterpret_cast<cgv2u64*>(gptr64(in_k) + j);
             if constexpr (PAIRS) {
-                r[e] = El{gptr64(b.in_k)[base + j] ^ flip, j};
-                V[j] = gptr64(b.in_v)[base + j];
+                const v2u64 v = *reinterpret_cast<cgv2u64*>(gptr64(in_v) + j);
+                r[2 * c] = El{k[0] ^ flip, j};
+                r[2 * c + 1] = El{k[1] ^ flip, j + 1u};
+                V[j] = v[0];
+                V[j + 1] = v[1];
             } else {
-                r[e] = El{gptr64(b.in_k)[base + j] ^ flip};
+                r[2 * c] = El{k[0] ^ flip};
+                r[2 * c + 1] = El{k[1] ^ flip};
             }
         } else {
-            r[e] = El::sentinel();
+#pragma unroll
+            for (uint32_t q = 0; q < 2u; ++q) {
+                const uint32_t jq = j + q;
+                if (jq < cnt) {
+                    if constexpr (PAIRS) {
+                        r[2 * c + q] = El{gptr64(in_k)[jq] ^ flip, jq};
+                        V[jq] = gptr64(in_v)[jq];
+                    } else {
+                        r[2 * c + q] = El{gptr64(in_k)[jq] ^ flip};
+                    }
+                } else {
+                    r[2 * c + q] = El::sentinel();
+                }
+            }
         }
     }
     wave_sort_blocked<E>(r, lane);
