@@ -70,14 +70,14 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort_keys(Phase ph, Bufs b, uin
 
     // The wave sorts whatever it holds, so each lane loads four consecutive
     // keys per 16-byte load (chunk c: positions c*256 + 4*lane ..), which
-    // covers the wave's CH keys in E/4 loads.
+    // covers the wave's CH keys in E/4 loads; the loads need only 4-byte
+    // alignment (a batch's segments start anywhere).
     Elem<false> r[E];
-    const bool vec_in = ((uintptr_t)in_k & 15u) == 0;
 #pragma unroll
     for (uint32_t c = 0; c < Q; ++c) {
         const uint32_t j = (uint32_t)wave * CH + c * 256u + 4u * ul;
-        if (vec_in && j + 4u <= cnt) {
-            const u32x4 v = *reinterpret_cast<const gu32x4*>(gptr(in_k) + j);
+        if (j + 4u <= cnt) {
+            const u32x4a4 v = *reinterpret_cast<cgu32x4a4*>(gptr(in_k) + j);
             r[4 * c] = {v[0] ^ flip};
             r[4 * c + 1] = {v[1] ^ flip};
             r[4 * c + 2] = {v[2] ^ flip};
@@ -175,13 +175,12 @@ __global__ __launch_bounds__(W * 64) void k_tile_sort_pairs(Phase ph, Bufs b, ui
     // as in the keys-only base case, four consecutive pairs per 16-byte load
     // (each tagged with its own tile position); values staged in LDS alike
     ElemKT r[E];
-    const bool vec_in = ((((uintptr_t)in_k) | (uintptr_t)in_v) & 15u) == 0;
 #pragma unroll
     for (uint32_t c = 0; c < Q; ++c) {
         const uint32_t j = (uint32_t)wave * CH + c * 256u + 4u * ul;
-        if (vec_in && j + 4u <= cnt) {
-            const u32x4 k = *reinterpret_cast<const gu32x4*>(gptr(in_k) + j);
-            const u32x4 v = *reinterpret_cast<const gu32x4*>(gptr(in_v) + j);
+        if (j + 4u <= cnt) {
+            const u32x4a4 k = *reinterpret_cast<cgu32x4a4*>(gptr(in_k) + j);
+            const u32x4a4 v = *reinterpret_cast<cgu32x4a4*>(gptr(in_v) + j);
 #pragma unroll
             for (uint32_t q = 0; q < 4u; ++q) r[4 * c + q] = ElemKT{kt_pack(k[q] ^ flip, j + q)};
             *reinterpret_cast<uint4*>(V + j) = make_uint4(v[0], v[1], v[2], v[3]);
